@@ -1,0 +1,163 @@
+/*
+ * sca.h -- C ABI of the MI355X (gfx950) SCA library.
+ *
+ * The library evaluates the semiclassical-approximation (SCA) potential of the
+ * half-filled ionic Hubbard model on an L x L periodic square lattice, its
+ * gradient, its ADAM minimisation and the density of states at the optimum
+ * (Sec. II of the paper: Hamiltonian Eq. (1), potential Eq. (7), DOS Eq. (8);
+ * the ADAM/autograd procedure described after Eq. (7) and in Sec. III).
+ *
+ *   N = L*L sites, site i = x + L*y, t the hopping, U > 0, Delta the ionic
+ *   amplitude (site potential +Delta/2 on (-1)^(x+y) = +1 sites, -Delta/2 on
+ *   the others), T > 0 the temperature, M = n_max Matsubara frequencies
+ *   w_n = (2n+1) pi T, n = 0..M-1 (the negative ones enter as the complex
+ *   conjugates of these, so each contributes twice).
+ *
+ *   H_s(phi) = -t K + (Delta/2) S - s diag(phi) [+ diag(onsite)],  s = +1, -1
+ *   A_ns     = i w_n I - H_s(phi)                       (complex symmetric)
+ *   Omega    = sum_i phi_i^2/U - 2T sum_s sum_n ln|det A_ns|
+ *   Omega~   = Omega + 2 N T sum_n ln w_n^2            (constant removed)
+ *   dOmega/dphi_i = 2 phi_i/U - 2T sum_s s sum_n Re (A_ns^-1)_ii
+ *   rho_s(w) = -(1/(pi N)) Im sum_i ((w + i eta) I - H_s)^-1_ii
+ *   |phi|    = |N^-1 sum_i (-1)^(x+y) phi_i|          (AF order parameter)
+ *
+ * Every ln|det| and diagonal of an inverse comes from a batched complex LU
+ * with partial pivoting (largest |Re|+|Im| in the column) on the GPU.
+ *
+ * Conventions common to all calls
+ *   - Array arguments are DEVICE pointers on the context's device, allocated
+ *     and owned by the caller (e.g. torch tensors).  Struct arguments
+ *     (params, options, results) are HOST pointers.
+ *   - Work is enqueued on the context's stream; each call returns only after
+ *     that stream has drained, so the returned status covers the device work.
+ *   - Parameters are validated before any device work; on error nothing is
+ *     written.  sca_last_error() gives a message for the calling thread.
+ *   - A context is not thread-safe; use one context per host thread/stream.
+ *   - All values are float64; `precision` selects the arithmetic of the LU
+ *     (SCA_FP64, or SCA_FP32_REFINED: complex64 factorisation with float64
+ *     refinement of ln|det| and diag(A^-1)).
+ */
+#ifndef SCA_H
+#define SCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define SCA_API __attribute__((visibility("default")))
+#else
+#define SCA_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sca_ctx sca_ctx;
+
+typedef enum {
+  SCA_OK = 0,
+  SCA_EINVAL = -1,       /* invalid argument (message in sca_last_error) */
+  SCA_ENOMEM = -2,       /* workspace would exceed the context's HBM budget */
+  SCA_EDEVICE = -3,      /* HIP runtime error or no usable gfx950 device */
+  SCA_ENUMERIC = -4,     /* non-finite Omega/gradient/phi or a singular matrix */
+  SCA_EUNSUPPORTED = -5  /* size/precision combination not built */
+} sca_status;
+
+typedef enum { SCA_FP64 = 0, SCA_FP32_REFINED = 1 } sca_precision;
+
+/* One SCA problem.  onsite: optional DEVICE array of N extra site
+ * potentials (a disordered lattice), or NULL (the paper's ionic model). */
+typedef struct {
+  int32_t L;          /* even, 2 <= L <= 64 */
+  int32_t n_max;      /* M >= 1 */
+  int32_t precision;  /* sca_precision */
+  int32_t reserved;   /* must be 0 */
+  double t, U, delta, T;
+  const double* onsite;
+} sca_params;
+
+typedef struct {
+  double lr, beta1, beta2, eps;  /* ADAM (Kingma-Ba) hyper-parameters */
+  double grad_tol;     /* stop early once max|g| < grad_tol (0: never) */
+  int32_t n_steps;     /* maximum number of ADAM updates */
+  int32_t check_every; /* host reads max|g| every k steps (0: only at end) */
+  int32_t t0;          /* ADAM step count already taken (resume); 0 fresh */
+  int32_t reserved;    /* must be 0 */
+} sca_adam_opts;
+
+typedef struct {
+  double omega;         /* Omega at the returned phi */
+  double omega_tilde;   /* Omega~ at the returned phi */
+  double af_order;      /* |phi| */
+  double max_abs_grad;  /* max_i |dOmega/dphi_i| at the returned phi */
+  double max_pivot_growth; /* max over matrices of max|u|/max|a| */
+  int32_t steps_done;   /* ADAM updates applied in this call */
+  int32_t flags;        /* SCA_FLAG_* bits */
+} sca_result;
+
+#define SCA_FLAG_NONFINITE 1    /* a non-finite value was produced */
+#define SCA_FLAG_PIVOT_GROWTH 2 /* FP32 growth above threshold: FP64 re-run */
+#define SCA_FLAG_CONVERGED 4    /* stopped by grad_tol */
+
+/* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  hbm_budget_bytes bounds the
+ * workspace the context may hold (0 = no bound).  Returns SCA_EDEVICE if
+ * the device is absent or not gfx950. */
+SCA_API sca_status sca_create(int device, void* hip_stream, size_t hbm_budget_bytes,
+                      sca_ctx** out);
+SCA_API void sca_destroy(sca_ctx* ctx);
+
+/* Device workspace (bytes) one problem needs: admission control for
+ * serving.  0 if the parameters are invalid. */
+SCA_API size_t sca_footprint_bytes(const sca_params* p);
+
+/* Omega and Omega~ (Eq. (7)) at phi[N] -> omega2[2] = {Omega, Omega~}. */
+SCA_API sca_status sca_potential(sca_ctx* ctx, const sca_params* p, const double* phi,
+                         double* omega2);
+
+/* Gradient dOmega/dphi -> grad[N]; omega2[2] as above, or NULL. */
+SCA_API sca_status sca_grad(sca_ctx* ctx, const sca_params* p, const double* phi,
+                    double* grad, double* omega2);
+
+/* ADAM minimisation of Omega from phi (in: phi0, out: final phi), with the
+ * first and second moments m[N], v[N] (in/out, zeros for a fresh start) so a
+ * run can resume where another stopped (opts->t0 = steps already taken).
+ * Every step runs on the device; the host only polls max|g| every
+ * check_every steps when grad_tol > 0.  res is filled on success. */
+SCA_API sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
+                          const sca_adam_opts* opts, double* phi, double* m,
+                          double* v, sca_result* res);
+
+/* Density of states per spin (Eq. (8), mu = 0): rho[2][n_w] (spin up first)
+ * at the n_w real frequencies w[n_w], broadening eta > 0. */
+SCA_API sca_status sca_dos(sca_ctx* ctx, const sca_params* p, const double* phi,
+                   const double* w, int32_t n_w, double eta, double* rho);
+
+/* The per-matrix terms behind the calls above, for arbitrary complex shifts
+ * z[n_z][2] (re, im): for both spins (up first) and every z_j,
+ *   logabsdet[2][n_z] = ln|det(z_j I - H_s)|
+ *   diag[2][n_z][N][2] = (z_j I - H_s)^-1_ii  (re, im interleaved). */
+SCA_API sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
+                             const double* phi, const double* z, int32_t n_z,
+                             double* logabsdet, double* diag);
+
+/* Differentiable split of sca_grad (a custom autograd backward): the
+ * forward factorises every A_ns and keeps what the backward needs in the
+ * caller's buffer `factors` of sca_factor_bytes(p) bytes; the backward then
+ * reads it instead of factorising again.  phi must be unchanged between the
+ * two calls. */
+SCA_API size_t sca_factor_bytes(const sca_params* p);
+SCA_API sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
+                         void* factors, double* omega2);
+SCA_API sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
+                                 const double* phi, void* factors,
+                                 double* grad);
+
+/* Message for the last error on this thread ("" if none). */
+SCA_API const char* sca_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCA_H */

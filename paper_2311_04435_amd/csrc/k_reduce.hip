@@ -1,0 +1,279 @@
+// Set-up, Matsubara/spin accumulation and the fused ADAM update.
+//
+//   Omega    = sum_i phi_i^2/U - 2T sum_b ln|det A_b|
+//   Omega~   = sum_i phi_i^2/U - 2T sum_b (ln|det A_b| - N ln w_n(b))
+//   g_i      = 2 phi_i/U - 2T (sum_n Re dg_up[n][i] - sum_n Re dg_dn[n][i])
+//
+// (potential Eq. (7); the factor 2 pairs +w_n with -w_n).  Every sum runs
+// in a fixed order that does not depend on the launch shape or on which
+// other problems share the batch, so a problem's result is the same alone
+// and in a mixed batch.  ADAM (Kingma & Ba, Algorithm 1; the paper's
+// optimizer, Sec. II after Eq. (7)) updates phi, m, v in the same pass.
+#include <math.h>
+#include "sca_common.h"
+#include "sca_kernels.h"
+
+namespace sca {
+
+namespace {
+constexpr int kSitesPerBlock = 64;
+constexpr int kBParts = 4;          // b-range split per site (fixed order)
+constexpr int kReduceThreads = kSitesPerBlock * kBParts;
+constexpr int kMaxChunks = 128;     // N <= 64 * 128 = 8192 sites
+constexpr double kPi = 3.14159265358979323846;
+}  // namespace
+
+__global__ void hvec_kernel(const ProbDesc* __restrict__ probs, int N,
+                            double* __restrict__ hbuf) {
+  const int p = blockIdx.y >> 1;
+  const int sidx = blockIdx.y & 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const ProbDesc P = probs[p];
+  const double s = sidx ? -1.0 : 1.0;
+  double h = 0.5 * P.delta * (double)stagger_sign(i, P.L) - s * P.phi[i];
+  if (P.onsite) h += P.onsite[i];
+  hbuf[P.hoff + sidx * N + i] = h;
+}
+
+hipError_t launch_hvec(const ProbDesc* probs, int nprob, int N, double* hbuf,
+                       hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hvec_kernel, dim3((N + 255) / 256, 2 * nprob), dim3(256),
+                     0, st, probs, N, hbuf);
+  return hipGetLastError();
+}
+
+__global__ void matsubara_desc_kernel(const ProbDesc* __restrict__ probs,
+                                      MatDesc* __restrict__ descs) {
+  const int p = blockIdx.y;
+  const ProbDesc P = probs[p];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 2 * P.M) return;
+  const int sidx = k / P.M, n = k % P.M;
+  MatDesc d;
+  d.zr = 0.0;
+  d.zi = (2.0 * n + 1.0) * kPi * P.T;
+  d.t = P.t;
+  d.hoff = P.hoff + sidx * P.N;
+  d.prob = p;
+  descs[P.mat_begin + k] = d;
+}
+
+hipError_t launch_matsubara_descs(const ProbDesc* probs, int nprob,
+                                    int max2M, MatDesc* descs,
+                                    hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(matsubara_desc_kernel, dim3((max2M + 255) / 256, nprob),
+                     dim3(256), 0, st, probs, descs);
+  return hipGetLastError();
+}
+
+// Partial results of one 64-site chunk of one problem.
+struct ChunkPartial {
+  double phi2;      // sum phi_i^2 (phi at which the terms were evaluated)
+  double stag;      // sum (-1)^(x+y) phi_i
+  double gmax;      // max |g_i|
+  int32_t nonfinite, pad_;
+};
+
+__global__ void __launch_bounds__(kReduceThreads)
+site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
+                   const double* __restrict__ dg, ChunkPartial* __restrict__ part,
+                   int adam_t, AdamHyper hy) {
+  const int p = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const ProbDesc P = probs[p];
+  const int tid = threadIdx.x;
+  const int site_l = tid % kSitesPerBlock;
+  const int bpart = tid / kSitesPerBlock;
+  const int i = chunk * kSitesPerBlock + site_l;
+  __shared__ double acc_s[kBParts][kSitesPerBlock];
+  __shared__ double red_s[3][kSitesPerBlock];
+  __shared__ int nf_s[kSitesPerBlock];
+
+  // sum over the problem's 2M matrices, split in kBParts contiguous ranges
+  // per spin; each range summed in increasing n
+  double acc = 0.0;
+  if (i < N && dg) {
+    const int M = P.M;
+    const int per = (M + kBParts - 1) / kBParts;
+    const int n0 = bpart * per, n1 = min(M, n0 + per);
+    double su = 0.0, sd = 0.0;
+    const double* up = dg + ((size_t)P.mat_begin * N + i) * 2;
+    const double* dn = dg + ((size_t)(P.mat_begin + M) * N + i) * 2;
+    for (int n = n0; n < n1; ++n) su += up[(size_t)n * N * 2];
+    for (int n = n0; n < n1; ++n) sd += dn[(size_t)n * N * 2];
+    acc = su - sd;
+  }
+  acc_s[bpart][site_l] = acc;
+  __syncthreads();
+  if (bpart == 0) {
+    double phi2 = 0.0, stag = 0.0, ga = 0.0;
+    int nf = 0;
+    if (i < N) {
+      double s = acc_s[0][site_l];
+      for (int q = 1; q < kBParts; ++q) s += acc_s[q][site_l];
+      const double ph = P.phi[i];
+      const double g = dg ? 2.0 * ph / P.U - 2.0 * P.T * s : 0.0;
+      if (P.grad && dg) P.grad[i] = g;
+      phi2 = ph * ph;
+      stag = (double)stagger_sign(i, P.L) * ph;
+      ga = fabs(g);
+      nf = !isfinite(g);
+      if (adam_t > 0 && dg) {
+        const double m = hy.beta1 * P.m[i] + (1.0 - hy.beta1) * g;
+        const double v = hy.beta2 * P.v[i] + (1.0 - hy.beta2) * g * g;
+        const double bc1 = 1.0 - pow(hy.beta1, (double)adam_t);
+        const double bc2 = 1.0 - pow(hy.beta2, (double)adam_t);
+        const double upd = hy.lr * (m / bc1) / (sqrt(v / bc2) + hy.eps);
+        P.m[i] = m;
+        P.v[i] = v;
+        const double nphi = ph - upd;
+        nf |= !isfinite(nphi);
+        P.phi_out[i] = nphi;
+      }
+    }
+    red_s[0][site_l] = phi2;
+    red_s[1][site_l] = stag;
+    red_s[2][site_l] = ga;
+    nf_s[site_l] = nf;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    int nf = 0;
+    for (int q = 0; q < kSitesPerBlock; ++q) {
+      a += red_s[0][q];
+      b += red_s[1][q];
+      c = fmax(c, red_s[2][q]);
+      nf |= nf_s[q];
+    }
+    ChunkPartial cp;
+    cp.phi2 = a; cp.stag = b; cp.gmax = c; cp.nonfinite = nf; cp.pad_ = 0;
+    part[p * kMaxChunks + chunk] = cp;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+problem_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
+                      const double* __restrict__ lad,
+                      const double* __restrict__ growth,
+                      const ChunkPartial* __restrict__ part, int nchunks,
+                      ProbStats* __restrict__ stats) {
+  const int p = blockIdx.x;
+  const ProbDesc P = probs[p];
+  const int tid = threadIdx.x;
+  __shared__ double s_full[256], s_red[256], s_gr[256];
+  // each thread sums a strided subset of the 2M matrices in increasing b
+  double full = 0.0, red = 0.0, gr = 0.0;
+  for (int k = tid; k < 2 * P.M; k += 256) {
+    const int n = k % P.M;
+    const double w = (2.0 * n + 1.0) * kPi * P.T;
+    const double l = lad[P.mat_begin + k];
+    full += l;
+    red += l - (double)N * log(w);
+    gr = fmax(gr, growth[P.mat_begin + k]);
+  }
+  s_full[tid] = full; s_red[tid] = red; s_gr[tid] = gr;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (tid < w) {
+      s_full[tid] += s_full[tid + w];
+      s_red[tid] += s_red[tid + w];
+      s_gr[tid] = fmax(s_gr[tid], s_gr[tid + w]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double phi2 = 0.0, stag = 0.0, gmax = 0.0;
+    int nf = 0;
+    for (int c = 0; c < nchunks; ++c) {
+      const ChunkPartial cp = part[p * kMaxChunks + c];
+      phi2 += cp.phi2; stag += cp.stag; gmax = fmax(gmax, cp.gmax);
+      nf |= cp.nonfinite;
+    }
+    ProbStats S;
+    S.omega = phi2 / P.U - 2.0 * P.T * s_full[0];
+    S.omega_tilde = phi2 / P.U - 2.0 * P.T * s_red[0];
+    S.max_abs_grad = gmax;
+    S.af_order = fabs(stag) / (double)N;
+    S.pivot_growth = s_gr[0];
+    nf |= !isfinite(S.omega) || !isfinite(S.omega_tilde);
+    S.nonfinite = nf;
+    S.pad_ = 0;
+    stats[p] = S;
+  }
+}
+
+size_t reduce_workspace_bytes(int nprob) {
+  return (size_t)nprob * kMaxChunks * sizeof(ChunkPartial);
+}
+
+int reduce_max_sites() { return kSitesPerBlock * kMaxChunks; }
+
+hipError_t launch_reduce(const ProbDesc* probs, int nprob, int N,
+                            const double* lad, const double* dg,
+                            const double* growth, ProbStats* stats, int adam_t,
+                            AdamHyper hyper, void* ws, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  const int nchunks = (N + kSitesPerBlock - 1) / kSitesPerBlock;
+  if (nchunks > kMaxChunks) return hipErrorInvalidValue;
+  ChunkPartial* part = static_cast<ChunkPartial*>(ws);
+  hipLaunchKernelGGL(site_reduce_kernel, dim3(nchunks, nprob),
+                     dim3(kReduceThreads), 0, st, probs, N, dg, part, adam_t,
+                     hyper);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(problem_reduce_kernel, dim3(nprob), dim3(256), 0, st,
+                     probs, N, lad, growth, part, nchunks, stats);
+  return hipGetLastError();
+}
+
+__global__ void dos_reduce_kernel(const double* __restrict__ dg, int n_w,
+                                  int N, double* __restrict__ rho) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (j >= n_w) return;
+  const double* x = dg + ((size_t)(s * n_w + j) * N) * 2;
+  double acc = 0.0;
+  for (int i = 0; i < N; ++i) acc += x[2 * i + 1];
+  rho[s * n_w + j] = -acc / (kPi * (double)N);
+}
+
+hipError_t launch_dos_reduce(const double* dg, int n_w, int N, double* rho,
+                             hipStream_t st) {
+  if (n_w <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dos_reduce_kernel, dim3((n_w + 127) / 128, 2), dim3(128),
+                     0, st, dg, n_w, N, rho);
+  return hipGetLastError();
+}
+
+}  // namespace sca
+
+namespace sca {
+
+__global__ void shift_desc_kernel(const double* __restrict__ z, int n_z,
+                                  double t, int hoff0, int N,
+                                  MatDesc* __restrict__ descs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sidx = blockIdx.y;
+  if (j >= n_z) return;
+  MatDesc d;
+  d.zr = z[2 * j];
+  d.zi = z[2 * j + 1];
+  d.t = t;
+  d.hoff = hoff0 + sidx * N;
+  d.prob = 0;
+  descs[sidx * n_z + j] = d;
+}
+
+hipError_t launch_shift_descs(const double* z, int n_z, double t, int hoff0,
+                              int N, MatDesc* descs, hipStream_t st) {
+  if (n_z <= 0) return hipSuccess;
+  hipLaunchKernelGGL(shift_desc_kernel, dim3((n_z + 255) / 256, 2), dim3(256),
+                     0, st, z, n_z, t, hoff0, N, descs);
+  return hipGetLastError();
+}
+
+}  // namespace sca

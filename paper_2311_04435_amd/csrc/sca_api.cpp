@@ -1,0 +1,556 @@
+// Host runtime and C ABI of the SCA library (see include/sca.h).
+//
+// A context owns one growable device workspace and a small pinned staging
+// buffer, and enqueues everything on the caller's stream.  One evaluation
+// of a problem set runs, all on the device:
+//   descriptors (once per call) -> h vectors -> batched factor + inverse
+//   diagonal -> Matsubara/spin reduction (+ fused ADAM update)
+// The host only reads back the per-problem statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sca.h"
+#include "sca_common.h"
+#include "sca_kernels.h"
+#include "sca_runtime.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+sca_status fail(sca_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(SCA_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct sca_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+};
+
+namespace sca {
+
+sca_status validate_params(const sca_params* p) {
+  if (!p) return fail(SCA_EINVAL, "params is NULL");
+  if (p->L < 2 || p->L > kMaxL || (p->L & 1))
+    return fail(SCA_EINVAL, "L=%d: must be even and in [2, %d]", p->L, kMaxL);
+  if (p->n_max < 1 || p->n_max > kMaxNmax)
+    return fail(SCA_EINVAL, "n_max=%d: must be in [1, %d]", p->n_max, kMaxNmax);
+  if (p->precision != SCA_FP64 && p->precision != SCA_FP32_REFINED)
+    return fail(SCA_EINVAL, "precision=%d: unknown", p->precision);
+  if (p->reserved != 0) return fail(SCA_EINVAL, "reserved field must be 0");
+  if (!std::isfinite(p->t) || !std::isfinite(p->delta))
+    return fail(SCA_EINVAL, "t and delta must be finite");
+  if (!(p->U > 0.0) || !std::isfinite(p->U))
+    return fail(SCA_EINVAL, "U=%g: must be finite and > 0", p->U);
+  if (!(p->T > 0.0) || !std::isfinite(p->T))
+    return fail(SCA_EINVAL, "T=%g: must be finite and > 0", p->T);
+  const int N = p->L * p->L;
+  if (!path_supported(N, p->precision))
+    return fail(SCA_EUNSUPPORTED, "N=%d with precision %d is not built", N,
+                p->precision);
+  return SCA_OK;
+}
+
+}  // namespace sca
+
+using namespace sca;
+
+namespace {
+
+sca_status check_dev_ptr(const sca_ctx* ctx, const void* ptr, const char* name,
+                         bool allow_null = false) {
+  if (!ptr) {
+    if (allow_null) return SCA_OK;
+    return fail(SCA_EINVAL, "%s is NULL", name);
+  }
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SCA_EINVAL, "%s is not a device pointer", name);
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(SCA_EINVAL, "%s is not device memory", name);
+  if (attr.device != ctx->device)
+    return fail(SCA_EINVAL, "%s lives on device %d, context on %d", name,
+                attr.device, ctx->device);
+  return SCA_OK;
+}
+
+sca_status ensure_ws(sca_ctx* ctx, size_t bytes) {
+  if (ctx->budget && bytes > ctx->budget)
+    return fail(SCA_ENOMEM, "workspace of %zu bytes exceeds the budget of %zu",
+                bytes, ctx->budget);
+  if (bytes <= ctx->ws_bytes) return SCA_OK;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (ctx->ws) HIP_TRY(hipFree(ctx->ws));
+  ctx->ws = nullptr;
+  ctx->ws_bytes = 0;
+  hipError_t e = hipMalloc(&ctx->ws, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SCA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes,
+                hipGetErrorString(e));
+  }
+  ctx->ws_bytes = bytes;
+  return SCA_OK;
+}
+
+sca_status ensure_pinned(sca_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->pinned_bytes) return SCA_OK;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
+  ctx->pinned = nullptr;
+  ctx->pinned_bytes = 0;
+  HIP_TRY(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
+  ctx->pinned_bytes = bytes;
+  return SCA_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+ProbDesc make_prob(const sca_params* p, const double* phi, double* grad) {
+  ProbDesc P{};
+  P.phi = phi;
+  P.onsite = p->onsite;
+  P.grad = grad;
+  P.t = p->t; P.U = p->U; P.delta = p->delta; P.T = p->T;
+  P.L = p->L; P.N = p->L * p->L; P.M = p->n_max;
+  P.mat_begin = 0;
+  P.hoff = 0;
+  return P;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- engine ----
+
+namespace sca {
+
+// Workspace carve-up for one batch of `nprob` problems of N sites with B
+// matrices in total.
+struct Carve {
+  ProbDesc* probs; MatDesc* descs; double* hbuf; double* lad; double* growth;
+  double* dg; void* rws; ProbStats* stats; void* fact;
+  size_t total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static Carve carve(char* base, int nprob, int N, int B, int precision,
+                   bool own_dg, bool own_lad, size_t fact_bytes) {
+  Carve c{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return base ? base + o : nullptr; };
+  c.probs = (ProbDesc*)take(sizeof(ProbDesc) * nprob);
+  c.descs = (MatDesc*)take(sizeof(MatDesc) * (size_t)B);
+  c.hbuf = (double*)take(sizeof(double) * 2 * (size_t)nprob * N);
+  c.lad = own_lad ? (double*)take(sizeof(double) * (size_t)B) : nullptr;
+  c.growth = (double*)take(sizeof(double) * (size_t)B);
+  c.dg = own_dg ? (double*)take(sizeof(double) * 2 * (size_t)B * N) : nullptr;
+  c.rws = take(reduce_workspace_bytes(nprob));
+  c.stats = (ProbStats*)take(sizeof(ProbStats) * nprob);
+  c.fact = fact_bytes ? (void*)take(fact_bytes) : nullptr;
+  (void)precision;
+  c.total = off;
+  return c;
+}
+
+size_t footprint(int N, int M, int precision) {
+  const int B = 2 * M;
+  Carve c = carve(nullptr, 1, N, B, precision, true, true,
+                  factor_workspace_bytes(N, B, precision));
+  return c.total;
+}
+
+}  // namespace sca
+
+namespace {
+
+// Evaluate the terms of `nprob` problems (same L) already described in
+// host_probs; adam_t > 0 applies one fused ADAM update per problem.
+// If `descs_ready`, the descriptors in the workspace are reused.
+sca_status run_batch(sca_ctx* ctx, Carve& c, const ProbDesc* host_probs,
+                     int nprob, int L, int B, int max2M, int precision,
+                     int adam_t, AdamHyper hy, bool upload) {
+  const int N = L * L;
+  hipStream_t st = ctx->stream;
+  if (upload) {
+    sca_status s = ensure_pinned(ctx, sizeof(ProbDesc) * nprob);
+    if (s) return s;
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(ctx->pinned, host_probs, sizeof(ProbDesc) * nprob);
+    HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof(ProbDesc) * nprob,
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_matsubara_descs(c.probs, nprob, max2M, c.descs, st));
+  }
+  HIP_TRY(launch_hvec(c.probs, nprob, N, c.hbuf, st));
+  HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, L, precision, c.lad, c.dg,
+                       c.growth, c.fact, st));
+  HIP_TRY(launch_reduce(c.probs, nprob, N, c.lad, c.dg, c.growth, c.stats,
+                        adam_t, hy, c.rws, st));
+  return SCA_OK;
+}
+
+sca_status read_stats(sca_ctx* ctx, const Carve& c, int nprob,
+                      ProbStats* out) {
+  sca_status s = ensure_pinned(ctx, sizeof(ProbStats) * nprob);
+  if (s) return s;
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, c.stats, sizeof(ProbStats) * nprob,
+                         hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  std::memcpy(out, ctx->pinned, sizeof(ProbStats) * nprob);
+  return SCA_OK;
+}
+
+sca_status begin_call(sca_ctx* ctx, const sca_params* p) {
+  g_err.clear();
+  if (!ctx) return fail(SCA_EINVAL, "context is NULL");
+  sca_status s = validate_params(p);
+  if (s) return s;
+  return check_dev_ptr(ctx, p->onsite, "params.onsite", true);
+}
+
+sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
+                       double* grad, double* omega2, ProbStats* st_out) {
+  const int N = p->L * p->L, M = p->n_max, B = 2 * M;
+  Carve c0 = carve(nullptr, 1, N, B, p->precision, true, true,
+                   factor_workspace_bytes(N, B, p->precision));
+  sca_status s = ensure_ws(ctx, c0.total);
+  if (s) return s;
+  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, true, true,
+                  factor_workspace_bytes(N, B, p->precision));
+  ProbDesc P = make_prob(p, phi, grad);
+  s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, 0, AdamHyper{}, true);
+  if (s) return s;
+  ProbStats S;
+  s = read_stats(ctx, c, 1, &S);
+  if (s) return s;
+  if (omega2) {
+    double o2[2] = {S.omega, S.omega_tilde};
+    HIP_TRY(hipMemcpyAsync(omega2, o2, sizeof o2, hipMemcpyHostToDevice,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  if (st_out) *st_out = S;
+  if (S.nonfinite)
+    return fail(SCA_ENUMERIC, "non-finite potential or gradient");
+  return SCA_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- C ABI -----
+
+extern "C" {
+
+sca_status sca_create(int device, void* hip_stream, size_t hbm_budget_bytes,
+                      sca_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(SCA_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) {
+    (void)hipGetLastError();
+    return fail(SCA_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= n)
+    return fail(SCA_EINVAL, "device %d out of range [0, %d)", device, n);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SCA_EDEVICE, "device %d is %s; this library is built for gfx950",
+                device, prop.gcnArchName);
+  sca_ctx* ctx = new sca_ctx;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->budget = hbm_budget_bytes;
+  *out = ctx;
+  return SCA_OK;
+}
+
+void sca_destroy(sca_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+size_t sca_footprint_bytes(const sca_params* p) {
+  std::string saved = g_err;
+  if (validate_params(p) != SCA_OK) return 0;
+  g_err = saved;
+  return footprint(p->L * p->L, p->n_max, p->precision);
+}
+
+sca_status sca_potential(sca_ctx* ctx, const sca_params* p, const double* phi,
+                         double* omega2) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  DeviceGuard g(ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if ((s = check_dev_ptr(ctx, omega2, "omega2"))) return s;
+  return eval_single(ctx, p, phi, nullptr, omega2, nullptr);
+}
+
+sca_status sca_grad(sca_ctx* ctx, const sca_params* p, const double* phi,
+                    double* grad, double* omega2) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  DeviceGuard g(ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
+  if ((s = check_dev_ptr(ctx, omega2, "omega2", true))) return s;
+  return eval_single(ctx, p, phi, grad, omega2, nullptr);
+}
+
+sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
+                          const sca_adam_opts* o, double* phi, double* m,
+                          double* v, sca_result* res) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  if (!o) return fail(SCA_EINVAL, "opts is NULL");
+  if (!res) return fail(SCA_EINVAL, "result is NULL");
+  if (o->n_steps < 0 || o->check_every < 0 || o->t0 < 0 || o->reserved != 0)
+    return fail(SCA_EINVAL, "n_steps, check_every, t0 must be >= 0");
+  if (!(o->lr > 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) ||
+      !(o->beta2 >= 0.0 && o->beta2 < 1.0) || !(o->eps >= 0.0) ||
+      !(o->grad_tol >= 0.0))
+    return fail(SCA_EINVAL, "invalid ADAM hyper-parameters");
+  DeviceGuard g(ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if ((s = check_dev_ptr(ctx, m, "m"))) return s;
+  if ((s = check_dev_ptr(ctx, v, "v"))) return s;
+
+  const int N = p->L * p->L, M = p->n_max, B = 2 * M;
+  const size_t fb = factor_workspace_bytes(N, B, p->precision);
+  Carve c0 = carve(nullptr, 1, N, B, p->precision, true, true, fb);
+  if ((s = ensure_ws(ctx, c0.total))) return s;
+  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, true, true, fb);
+  ProbDesc P = make_prob(p, phi, nullptr);
+  P.m = m; P.v = v; P.phi_out = phi;
+  AdamHyper hy{o->lr, o->beta1, o->beta2, o->eps};
+  std::memset(res, 0, sizeof *res);
+  int done = 0;
+  bool converged = false;
+  for (int k = 1; k <= o->n_steps; ++k) {
+    s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, o->t0 + k, hy,
+                  k == 1);
+    if (s) return s;
+    done = k;
+    if (o->check_every > 0 && k % o->check_every == 0) {
+      ProbStats S;
+      if ((s = read_stats(ctx, c, 1, &S))) return s;
+      if (S.nonfinite) {
+        res->steps_done = done;
+        res->flags |= SCA_FLAG_NONFINITE;
+        return fail(SCA_ENUMERIC, "non-finite value at step %d", o->t0 + k);
+      }
+      if (o->grad_tol > 0.0 && S.max_abs_grad < o->grad_tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  // statistics at the returned phi
+  s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, 0, hy, done == 0);
+  if (s) return s;
+  ProbStats S;
+  if ((s = read_stats(ctx, c, 1, &S))) return s;
+  res->omega = S.omega;
+  res->omega_tilde = S.omega_tilde;
+  res->af_order = S.af_order;
+  res->max_abs_grad = S.max_abs_grad;
+  res->max_pivot_growth = S.pivot_growth;
+  res->steps_done = done;
+  if (converged) res->flags |= SCA_FLAG_CONVERGED;
+  if (S.nonfinite) {
+    res->flags |= SCA_FLAG_NONFINITE;
+    return fail(SCA_ENUMERIC, "non-finite value in the solve");
+  }
+  return SCA_OK;
+}
+
+sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
+                             const double* phi, const double* z, int32_t n_z,
+                             double* logabsdet, double* diag) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  if (n_z < 1 || n_z > kMaxShifts)
+    return fail(SCA_EINVAL, "n_z=%d: must be in [1, %d]", n_z, kMaxShifts);
+  DeviceGuard g(ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if ((s = check_dev_ptr(ctx, z, "z"))) return s;
+  if ((s = check_dev_ptr(ctx, logabsdet, "logabsdet"))) return s;
+  if ((s = check_dev_ptr(ctx, diag, "diag"))) return s;
+  const int N = p->L * p->L, B = 2 * n_z;
+  const size_t fb = factor_workspace_bytes(N, B, p->precision);
+  Carve c0 = carve(nullptr, 1, N, B, p->precision, false, false, fb);
+  if ((s = ensure_ws(ctx, c0.total))) return s;
+  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, false, false, fb);
+  ProbDesc P = make_prob(p, phi, nullptr);
+  hipStream_t st = ctx->stream;
+  if ((s = ensure_pinned(ctx, sizeof P))) return s;
+  HIP_TRY(hipStreamSynchronize(st));
+  std::memcpy(ctx->pinned, &P, sizeof P);
+  HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
+  HIP_TRY(launch_shift_descs(z, n_z, p->t, 0, N, c.descs, st));
+  HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, p->L, p->precision, logabsdet,
+                       diag, c.growth, c.fact, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SCA_OK;
+}
+
+sca_status sca_dos(sca_ctx* ctx, const sca_params* p, const double* phi,
+                   const double* w, int32_t n_w, double eta, double* rho) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  if (n_w < 1 || n_w > kMaxShifts)
+    return fail(SCA_EINVAL, "n_w=%d: must be in [1, %d]", n_w, kMaxShifts);
+  if (!(eta > 0.0) || !std::isfinite(eta))
+    return fail(SCA_EINVAL, "eta=%g: must be finite and > 0", eta);
+  DeviceGuard g(ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if ((s = check_dev_ptr(ctx, w, "w"))) return s;
+  if ((s = check_dev_ptr(ctx, rho, "rho"))) return s;
+  const int N = p->L * p->L, B = 2 * n_w;
+  const size_t fb = factor_workspace_bytes(N, B, p->precision);
+  // shifts z_j = w_j + i eta live after the carve
+  Carve c0 = carve(nullptr, 1, N, B, p->precision, true, true, fb);
+  const size_t zoff = c0.total;
+  if ((s = ensure_ws(ctx, zoff + align256(sizeof(double) * 2 * n_w)))) return s;
+  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, true, true, fb);
+  double* zbuf = (double*)((char*)ctx->ws + zoff);
+  ProbDesc P = make_prob(p, phi, nullptr);
+  hipStream_t st = ctx->stream;
+  if ((s = ensure_pinned(ctx, sizeof P))) return s;
+  HIP_TRY(hipStreamSynchronize(st));
+  std::memcpy(ctx->pinned, &P, sizeof P);
+  HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_make_shifts(w, n_w, eta, zbuf, st));
+  HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
+  HIP_TRY(launch_shift_descs(zbuf, n_w, p->t, 0, N, c.descs, st));
+  HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, p->L, p->precision, c.lad, c.dg,
+                       c.growth, c.fact, st));
+  HIP_TRY(launch_dos_reduce(c.dg, n_w, N, rho, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SCA_OK;
+}
+
+size_t sca_factor_bytes(const sca_params* p) {
+  std::string saved = g_err;
+  if (validate_params(p) != SCA_OK) return 0;
+  g_err = saved;
+  const int N = p->L * p->L, B = 2 * p->n_max;
+  return autograd_factor_bytes(N, B, p->precision);
+}
+
+sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
+                         void* factors, double* omega2) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  DeviceGuard g(ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
+  if ((s = check_dev_ptr(ctx, omega2, "omega2"))) return s;
+  const int N = p->L * p->L, M = p->n_max, B = 2 * M;
+  Carve c0 = carve(nullptr, 1, N, B, p->precision, false, false, 0);
+  if ((s = ensure_ws(ctx, c0.total))) return s;
+  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, false, false, 0);
+  AutogradLayout lay = autograd_layout(factors, N, B, p->precision);
+  c.lad = lay.lad;
+  c.dg = lay.dg;
+  c.fact = lay.fact;
+  ProbDesc P = make_prob(p, phi, nullptr);
+  hipStream_t st = ctx->stream;
+  if ((s = ensure_pinned(ctx, sizeof P))) return s;
+  HIP_TRY(hipStreamSynchronize(st));
+  std::memcpy(ctx->pinned, &P, sizeof P);
+  HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_matsubara_descs(c.probs, 1, B, c.descs, st));
+  HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
+  HIP_TRY(factor_forward(c.descs, c.hbuf, B, N, p->L, p->precision, c.lad,
+                         c.dg, c.growth, c.fact, st));
+  HIP_TRY(launch_reduce_omega(c.probs, 1, N, c.lad, c.growth, c.stats, c.rws, st));
+  ProbStats S;
+  if ((s = read_stats(ctx, c, 1, &S))) return s;
+  double o2[2] = {S.omega, S.omega_tilde};
+  HIP_TRY(hipMemcpyAsync(omega2, o2, sizeof o2, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (!std::isfinite(S.omega) || !std::isfinite(S.omega_tilde))
+    return fail(SCA_ENUMERIC, "non-finite potential");
+  return SCA_OK;
+}
+
+sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
+                                 const double* phi, void* factors,
+                                 double* grad) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  DeviceGuard g(ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
+  if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
+  const int N = p->L * p->L, M = p->n_max, B = 2 * M;
+  Carve c0 = carve(nullptr, 1, N, B, p->precision, false, false, 0);
+  if ((s = ensure_ws(ctx, c0.total))) return s;
+  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, false, false, 0);
+  AutogradLayout lay = autograd_layout(factors, N, B, p->precision);
+  ProbDesc P = make_prob(p, phi, grad);
+  hipStream_t st = ctx->stream;
+  if ((s = ensure_pinned(ctx, sizeof P))) return s;
+  HIP_TRY(hipStreamSynchronize(st));
+  std::memcpy(ctx->pinned, &P, sizeof P);
+  HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
+  HIP_TRY(factor_backward(B, N, p->precision, lay.lad, lay.dg, lay.fact, st));
+  HIP_TRY(launch_reduce(c.probs, 1, N, lay.lad, lay.dg, lay.growth, c.stats, 0,
+                        AdamHyper{}, c.rws, st));
+  ProbStats S;
+  if ((s = read_stats(ctx, c, 1, &S))) return s;
+  if (S.nonfinite) return fail(SCA_ENUMERIC, "non-finite gradient");
+  return SCA_OK;
+}
+
+const char* sca_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

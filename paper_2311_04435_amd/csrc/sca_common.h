@@ -1,0 +1,58 @@
+// Shared device/host definitions of the SCA library (gfx950).
+//
+// A batch is a list of complex matrices A_b = z_b I - H_b, where
+//   H_b = -t_b K + diag(h_b),   K = periodic nearest-neighbour adjacency of
+// the L x L lattice (site i = x + L*y; K_ij counts the directions +-x, +-y
+// that map i to j, so K_ij = 2 on L = 2).  h_b is the real diagonal
+// (Delta/2) (-1)^(x+y) - s phi_i (+ onsite_i) of spin s (Sec. II, Eq. (1)
+// after the static Hubbard-Stratonovich decoupling of Eqs. (5)-(7)).
+// A is generated on chip from (z_b, t_b, h_b); it is never read from HBM.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sca {
+
+struct MatDesc {
+  double zr, zi;   // shift z_b
+  double t;        // hopping
+  int32_t hoff;    // offset (doubles) of h_b in the diagonal buffer
+  int32_t prob;    // owning problem
+};
+
+struct ProbDesc {
+  const double* phi;     // [N] field
+  const double* onsite;  // [N] extra site potential or nullptr
+  double* grad;          // [N] gradient output (may be nullptr)
+  double* m;             // [N] ADAM first moment (adam only)
+  double* v;             // [N] ADAM second moment (adam only)
+  double* phi_out;       // [N] updated field (adam only; may alias phi)
+  double t, U, delta, T;
+  int32_t L, N, M;       // lattice side, sites, Matsubara count
+  int32_t mat_begin;     // matrices [mat_begin, mat_begin + 2M): up then down
+  int32_t hoff;          // h vectors: up at hoff, down at hoff + N
+  int32_t pad_;
+};
+
+// Per-problem statistics written by the reduction kernel.
+struct ProbStats {
+  double omega, omega_tilde, max_abs_grad, af_order, pivot_growth;
+  int32_t nonfinite, pad_;
+};
+
+// Number of lattice directions d in {+x,-x,+y,-y} with j = i + d (mod L).
+__host__ __device__ inline int kmult(int i, int j, int L) {
+  int xi = i % L, yi = i / L, xj = j % L, yj = j / L;
+  int dx = xj - xi; if (dx < 0) dx += L;
+  int dy = yj - yi; if (dy < 0) dy += L;
+  int c = 0;
+  if (dy == 0) c += (dx == 1) + (dx == L - 1);
+  if (dx == 0) c += (dy == 1) + (dy == L - 1);
+  return c;
+}
+
+__host__ __device__ inline int stagger_sign(int i, int L) {
+  return (((i % L) + (i / L)) & 1) ? -1 : 1;
+}
+
+}  // namespace sca

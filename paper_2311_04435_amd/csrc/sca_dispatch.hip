@@ -1,0 +1,95 @@
+// Factorisation path selection.
+//   N <= 64  : fused small kernel (matrix in LDS), FP64 for both precisions
+//              (these matrices are too small for the FP32 route to pay).
+#include "sca_common.h"
+#include "sca_kernels.h"
+#include "sca_runtime.h"
+
+namespace sca {
+
+namespace {
+constexpr int kSmallMax = 64;
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+bool path_supported(int N, int precision) {
+  (void)precision;
+  return N >= 1 && N <= kSmallMax;
+}
+
+size_t factor_workspace_bytes(int N, int B, int precision) {
+  (void)B; (void)precision;
+  if (N <= kSmallMax) return 0;
+  return 0;
+}
+
+hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
+                        int L, int precision, double* lad, double* dg,
+                        double* growth, void* fact, hipStream_t st) {
+  (void)precision; (void)fact;
+  if (N <= kSmallMax)
+    return launch_small_factor(descs, hbuf, B, N, L, lad, dg, growth, st);
+  return hipErrorInvalidValue;
+}
+
+size_t autograd_factor_bytes(int N, int B, int precision) {
+  (void)precision;
+  size_t bytes = align256(sizeof(double) * (size_t)B)        // lad
+               + align256(sizeof(double) * (size_t)B)        // growth
+               + align256(sizeof(double) * 2 * (size_t)B * N);  // dg
+  return bytes;
+}
+
+AutogradLayout autograd_layout(void* base, int N, int B, int precision) {
+  (void)precision;
+  char* p = static_cast<char*>(base);
+  AutogradLayout a;
+  a.lad = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * (size_t)B);
+  a.growth = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * (size_t)B);
+  a.dg = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * 2 * (size_t)B * N);
+  a.fact = nullptr;
+  return a;
+}
+
+hipError_t factor_forward(const MatDesc* descs, const double* hbuf, int B,
+                          int N, int L, int precision, double* lad, double* dg,
+                          double* growth, void* fact, hipStream_t st) {
+  // the small path forms diag(A^-1) in the same pass as the LU
+  return factor_batch(descs, hbuf, B, N, L, precision, lad, dg, growth, fact,
+                      st);
+}
+
+hipError_t factor_backward(int B, int N, int precision, const double* lad,
+                           double* dg, void* fact, hipStream_t st) {
+  (void)B; (void)lad; (void)dg; (void)fact; (void)st; (void)precision;
+  if (N <= kSmallMax) return hipSuccess;   // dg already complete
+  return hipErrorInvalidValue;
+}
+
+__global__ void make_shifts_kernel(const double* __restrict__ w, int n_w,
+                                   double eta, double* __restrict__ z) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_w) return;
+  z[2 * j] = w[j];
+  z[2 * j + 1] = eta;
+}
+
+hipError_t launch_make_shifts(const double* w, int n_w, double eta, double* z,
+                              hipStream_t st) {
+  if (n_w <= 0) return hipSuccess;
+  hipLaunchKernelGGL(make_shifts_kernel, dim3((n_w + 255) / 256), dim3(256), 0,
+                     st, w, n_w, eta, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_omega(const ProbDesc* probs, int nprob, int N,
+                               const double* lad, const double* growth,
+                               ProbStats* stats, void* ws, hipStream_t st) {
+  return launch_reduce(probs, nprob, N, lad, nullptr, growth, stats, 0,
+                       AdamHyper{}, ws, st);
+}
+
+}  // namespace sca

@@ -1,0 +1,47 @@
+// Kernel launchers of the SCA library (internal C++ interface).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "sca_common.h"
+
+namespace sca {
+
+// h vectors of every problem: h[hoff + s_idx*N + i] =
+//   (Delta/2)(-1)^(x+y) - s phi_i + onsite_i,  s_idx 0 -> s = +1, 1 -> s = -1
+hipError_t launch_hvec(const ProbDesc* probs, int nprob, int N, double* hbuf,
+                       hipStream_t st);
+
+// Matsubara descriptors of every problem: for b in [mat_begin, +2M),
+// z = i w_n (n = (b - mat_begin) mod M), spin up for the first M.
+hipError_t launch_matsubara_descs(const ProbDesc* probs, int nprob,
+                                  int max2M, MatDesc* descs, hipStream_t st);
+
+// Small fused path, N <= 64: per matrix ln|det A_b| -> lad[b],
+// diag(A_b^-1) -> dg[b][N][2], growth max|u|/max|a| -> growth[b].
+hipError_t launch_small_factor(const MatDesc* descs, const double* hbuf, int B,
+                               int N, int L, double* lad, double* dg,
+                               double* growth, hipStream_t st);
+
+// Reduction of the per-matrix terms into Omega, Omega~ and the gradient of
+// every problem, optionally followed by one ADAM update (adam_t > 0 is the
+// 1-based step count used for the bias corrections).  stats[p] receives
+// Omega, Omega~, max|g|, |phi| (of the phi the terms were evaluated at) and
+// the largest pivot growth of the problem's matrices.
+struct AdamHyper { double lr, beta1, beta2, eps; };
+hipError_t launch_reduce(const ProbDesc* probs, int nprob, int N,
+                         const double* lad, const double* dg,
+                         const double* growth, ProbStats* stats, int adam_t,
+                         AdamHyper hyper, void* ws, hipStream_t st);
+size_t reduce_workspace_bytes(int nprob);
+int reduce_max_sites();
+
+// Descriptors for arbitrary shifts: b = s_idx * n_z + j, z = (z[2j], z[2j+1]),
+// h vector of spin s_idx at hoff0 + s_idx * N.
+hipError_t launch_shift_descs(const double* z, int n_z, double t, int hoff0,
+                              int N, MatDesc* descs, hipStream_t st);
+
+// DOS reduction: rho[s][j] = -(1/(pi N)) sum_i Im dg[b][i][1] for the
+// matrix b = s*n_w + j of a DOS batch.
+hipError_t launch_dos_reduce(const double* dg, int n_w, int N, double* rho,
+                             hipStream_t st);
+
+}  // namespace sca

@@ -1,0 +1,51 @@
+// Dispatch layer between the C ABI and the kernels: picks the factorisation
+// path from N and the precision and sizes its scratch memory.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include "sca_common.h"
+
+namespace sca {
+
+constexpr int kMaxL = 64;           // N <= 4096 sites
+constexpr int kMaxNmax = 1 << 16;   // Matsubara frequencies per spin
+constexpr int kMaxShifts = 1 << 20; // shifts per sca_dos / sca_shifted_terms
+
+// Whether a factorisation path exists for N sites at `precision`.
+bool path_supported(int N, int precision);
+
+// Scratch (bytes) the factorisation of B matrices of N sites needs beyond
+// the per-matrix outputs (0 for the fused small path).
+size_t factor_workspace_bytes(int N, int B, int precision);
+
+// ln|det A_b| -> lad[b], diag(A_b^-1) -> dg[b][N][2] (re, im), pivot growth
+// -> growth[b], for the B matrices described by descs.  `fact` is the
+// scratch of factor_workspace_bytes(N, B, precision) bytes.
+hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
+                        int L, int precision, double* lad, double* dg,
+                        double* growth, void* fact, hipStream_t st);
+
+// Autograd split of factor_batch.  The forward writes lad and growth and
+// keeps in `fact` (and, for the fused small path, in dg) what the backward
+// needs; the backward completes dg from it.
+struct AutogradLayout { double* lad; double* growth; double* dg; void* fact; };
+size_t autograd_factor_bytes(int N, int B, int precision);
+AutogradLayout autograd_layout(void* base, int N, int B, int precision);
+hipError_t factor_forward(const MatDesc* descs, const double* hbuf, int B,
+                          int N, int L, int precision, double* lad, double* dg,
+                          double* growth, void* fact, hipStream_t st);
+hipError_t factor_backward(int B, int N, int precision, const double* lad,
+                           double* dg, void* fact, hipStream_t st);
+
+// Omega, Omega~ of every problem without the gradient (dg not read).
+hipError_t launch_reduce_omega(const ProbDesc* probs, int nprob, int N,
+                               const double* lad, const double* growth,
+                               ProbStats* stats, void* ws, hipStream_t st);
+
+// z[2j] = w[j], z[2j+1] = eta.
+hipError_t launch_make_shifts(const double* w, int n_w, double eta, double* z,
+                              hipStream_t st);
+
+size_t footprint(int N, int M, int precision);
+
+}  // namespace sca
