@@ -83,8 +83,12 @@ typedef struct {
   int32_t n_steps;     /* maximum number of ADAM updates */
   int32_t check_every; /* host reads max|g| every k steps (0: only at end) */
   int32_t t0;          /* ADAM step count already taken (resume); 0 fresh */
-  int32_t reserved;    /* must be 0 */
+  int32_t flags;       /* SCA_ADAM_* bits, 0 by default */
 } sca_adam_opts;
+
+/* Skip the evaluation at the returned phi: the result then describes the
+ * last phi the loop evaluated (the input of the final update). */
+#define SCA_ADAM_NO_FINAL_EVAL 1
 
 typedef struct {
   double omega;         /* Omega at the returned phi */
@@ -153,6 +157,23 @@ SCA_API sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double
 SCA_API sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
                                  const double* phi, void* factors,
                                  double* grad);
+
+/* Kernel timing (tracing).  sca_profile(ctx, 1) resets the counters and
+ * brackets every later kernel launch of this context with HIP events on its
+ * stream; sca_profile(ctx, 0) stops.  sca_profile_read fills HOST arrays of
+ * SCA_PROFILE_SLOTS entries with the accumulated milliseconds and launch
+ * counts per kernel class (SCA_K_*). */
+#define SCA_PROFILE_SLOTS 8
+#define SCA_K_SMALL 0   /* fused small-lattice factor + inverse diagonal */
+#define SCA_K_LU 1      /* blocked LU with partial pivoting */
+#define SCA_K_TRTRI 2   /* blocked U^-1 and L^-1 */
+#define SCA_K_DIAGDOT 3 /* diagonal of A^-1 from U^-1 and L^-1 */
+#define SCA_K_REDUCE 4  /* Matsubara/spin reduction and ADAM update */
+#define SCA_K_SETUP 5   /* descriptors and diagonal vectors */
+#define SCA_K_REFINE 6  /* FP64 refinement of the FP32 route */
+SCA_API sca_status sca_profile(sca_ctx* ctx, int enable);
+SCA_API sca_status sca_profile_read(sca_ctx* ctx, double* total_ms,
+                                    int64_t* launches);
 
 /* Message for the last error on this thread ("" if none). */
 SCA_API const char* sca_last_error(void);

@@ -38,7 +38,7 @@ from .lu import (lu_pivoted, logabsdet_lu, inverse_lu, diag_inverse_lu,
 from .spectral import (omega_spectral, grad_spectral, dos_spectral,
                        terms_spectral)
 from .api import (omega_tilde, omega_full, grad, af_order, dos, adam_solve,
-                  shifted_terms, omega_tilde_d, grad_d)
+                  shifted_terms, shifted_terms_s, omega_tilde_d, grad_d)
 from .adam import AdamState, adam_step
 
 __all__ = [
@@ -47,5 +47,6 @@ __all__ = [
     "diag_inverse_lu", "leibniz_det", "adjugate_diag", "omega_spectral",
     "grad_spectral", "dos_spectral", "terms_spectral", "omega_tilde",
     "omega_full", "grad", "af_order", "dos", "adam_solve", "shifted_terms",
+    "shifted_terms_s",
     "omega_tilde_d", "grad_d", "AdamState", "adam_step",
 ]

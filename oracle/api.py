@@ -11,7 +11,7 @@ import numpy as np
 from .adam import AdamState, adam_step
 from .lu import lu_pivoted, logabsdet_lu, inverse_lu
 from .model import hamiltonian, matsubara, stagger_signs
-from .spectral import terms_spectral, dos_spectral
+from .spectral import terms_spectral, dos_spectral, shifted_terms_spectral
 
 
 def _unpack(p):
@@ -49,6 +49,12 @@ def shifted_terms(p, phi, z, spin, onsite=None):
         lad[j] = logabsdet_lu(LU)
         dg[j] = np.diag(inverse_lu(LU, perm))
     return lad, dg
+
+
+def shifted_terms_s(p, phi, z, spin, onsite=None):
+    """Route S for arbitrary complex shifts (same outputs as shifted_terms)."""
+    L, t, U, delta, T, M = _unpack(p)
+    return shifted_terms_spectral(L, t, delta, phi, z, spin, onsite)
 
 
 def omega_tilde_d(p, phi, onsite=None) -> float:

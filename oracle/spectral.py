@@ -62,3 +62,13 @@ def dos_spectral(L, t, delta, phi, w, eta, onsite=None) -> np.ndarray:
         out[row] = (eta / np.pi / ((w[:, None] - e[None, :]) ** 2 + eta * eta)
                     ).mean(axis=1)
     return out
+
+
+def shifted_terms_spectral(L, t, delta, phi, z, spin, onsite=None):
+    """(ln|det(z_j I - H_s)|, diag((z_j I - H_s)^-1)) from the spectrum:
+    sum_k ln|z - e_k| and sum_k psi_k(i)^2 / (z - e_k)."""
+    e, psi = _eig(L, t, delta, phi, spin, onsite)
+    z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
+    lad = np.log(np.abs(z[:, None] - e[None, :])).sum(axis=1)
+    dg = (1.0 / (z[:, None] - e[None, :])) @ (psi * psi).T
+    return lad, dg

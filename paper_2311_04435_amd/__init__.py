@@ -118,10 +118,13 @@ class Context:
     def adam_solve(self, p: Params, phi: torch.Tensor, m: torch.Tensor,
                    v: torch.Tensor, n_steps: int, lr: float = 0.01,
                    beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
-                   grad_tol: float = 0.0, check_every: int = 0, t0: int = 0):
-        """In-place ADAM on phi, m, v; returns the sca_result as a dict."""
+                   grad_tol: float = 0.0, check_every: int = 0, t0: int = 0,
+                   final_eval: bool = True):
+        """In-place ADAM on phi, m, v; returns the sca_result as a dict.
+        final_eval=False skips the evaluation at the returned phi."""
+        flags = 0 if final_eval else _lib.SCA_ADAM_NO_FINAL_EVAL
         opts = _lib.AdamOpts(lr, beta1, beta2, eps, grad_tol, n_steps,
-                             check_every, t0, 0)
+                             check_every, t0, flags)
         res = _lib.Result()
         _lib.check(_lib.lib.sca_adam_solve(
             self._h, C.byref(p.c()), C.byref(opts),
@@ -151,6 +154,18 @@ class Context:
             self._h, C.byref(p.c()), _dev(phi, p.N, "phi").data_ptr(),
             z.data_ptr(), n_z, lad.data_ptr(), dg.data_ptr()))
         return lad, torch.view_as_complex(dg)
+
+    def profile(self, enable: bool = True):
+        """Start (reset) or stop per-kernel HIP-event timing."""
+        _lib.check(_lib.lib.sca_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel class: (total ms, launches)} since profile(True)."""
+        ms = (C.c_double * _lib.PROFILE_SLOTS)()
+        n = (C.c_int64 * _lib.PROFILE_SLOTS)()
+        _lib.check(_lib.lib.sca_profile_read(self._h, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)
+                if n[i]}
 
     def factor_bytes(self, p: Params) -> int:
         return int(_lib.lib.sca_factor_bytes(C.byref(p.c())))

@@ -17,12 +17,16 @@ STATUS_NAMES = {0: "SCA_OK", -1: "SCA_EINVAL", -2: "SCA_ENOMEM",
                 -3: "SCA_EDEVICE", -4: "SCA_ENUMERIC", -5: "SCA_EUNSUPPORTED"}
 SCA_FP64, SCA_FP32_REFINED = 0, 1
 SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH, SCA_FLAG_CONVERGED = 1, 2, 4
+SCA_ADAM_NO_FINAL_EVAL = 1
+PROFILE_SLOTS = 8
+KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
+                  "refine", "spare")
 
 # Every symbol include/sca.h declares.
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",
            "sca_grad", "sca_adam_solve", "sca_dos", "sca_shifted_terms",
            "sca_factor_bytes", "sca_factorize", "sca_grad_from_factors",
-           "sca_last_error")
+           "sca_profile", "sca_profile_read", "sca_last_error")
 
 
 class Params(C.Structure):
@@ -37,7 +41,7 @@ class AdamOpts(C.Structure):
                 ("beta2", C.c_double), ("eps", C.c_double),
                 ("grad_tol", C.c_double), ("n_steps", C.c_int32),
                 ("check_every", C.c_int32), ("t0", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -57,7 +61,7 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing; build it with "
-            "`python -m paper_2311_04435_amd.build` (hipcc, gfx950)")
+            "`python paper_2311_04435_amd/build.py` (hipcc, gfx950)")
     lib = C.CDLL(LIB_PATH)
     vp, i32, dp = C.c_void_p, C.c_int32, C.c_void_p
     P, R, O = C.POINTER(Params), C.POINTER(Result), C.POINTER(AdamOpts)
@@ -73,6 +77,9 @@ def _load():
         "sca_factor_bytes": (C.c_size_t, [P]),
         "sca_factorize": (i32, [vp, P, dp, vp, dp]),
         "sca_grad_from_factors": (i32, [vp, P, dp, vp, dp]),
+        "sca_profile": (i32, [vp, C.c_int]),
+        "sca_profile_read": (i32, [vp, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_int64)]),
         "sca_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

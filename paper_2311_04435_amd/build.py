@@ -1,6 +1,6 @@
 """Build the gfx950 HIP library libsca.so in-tree with hipcc.
 
-    python -m paper_2311_04435_amd.build        (or build() from Python)
+    python paper_2311_04435_amd/build.py     (it does not import the package)
 
 Every source under csrc/ is compiled for gfx950 only, then linked into
 paper_2311_04435_amd/lib/libsca.so.  Packed-FP32 instructions are disabled

@@ -12,6 +12,7 @@
 #include <math.h>
 #include "sca_common.h"
 #include "sca_kernels.h"
+#include "sca_profile.h"
 
 namespace sca {
 
@@ -39,8 +40,10 @@ __global__ void hvec_kernel(const ProbDesc* __restrict__ probs, int N,
 hipError_t launch_hvec(const ProbDesc* probs, int nprob, int N, double* hbuf,
                        hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
+  mark_begin(K_SETUP, st);
   hipLaunchKernelGGL(hvec_kernel, dim3((N + 255) / 256, 2 * nprob), dim3(256),
                      0, st, probs, N, hbuf);
+  mark_end(K_SETUP, st);
   return hipGetLastError();
 }
 
@@ -220,6 +223,7 @@ hipError_t launch_reduce(const ProbDesc* probs, int nprob, int N,
   const int nchunks = (N + kSitesPerBlock - 1) / kSitesPerBlock;
   if (nchunks > kMaxChunks) return hipErrorInvalidValue;
   ChunkPartial* part = static_cast<ChunkPartial*>(ws);
+  mark_begin(K_REDUCE, st);
   hipLaunchKernelGGL(site_reduce_kernel, dim3(nchunks, nprob),
                      dim3(kReduceThreads), 0, st, probs, N, dg, part, adam_t,
                      hyper);
@@ -227,6 +231,7 @@ hipError_t launch_reduce(const ProbDesc* probs, int nprob, int N,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(problem_reduce_kernel, dim3(nprob), dim3(256), 0, st,
                      probs, N, lad, growth, part, nchunks, stats);
+  mark_end(K_REDUCE, st);
   return hipGetLastError();
 }
 

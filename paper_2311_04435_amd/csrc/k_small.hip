@@ -12,6 +12,7 @@
 // cost is latency (barriers), not flops.
 #include "sca_common.h"
 #include "sca_kernels.h"
+#include "sca_profile.h"
 
 namespace sca {
 
@@ -192,6 +193,11 @@ hipError_t launch_small_factor(const MatDesc* descs, const double* hbuf, int B,
                                int N, int L, double* lad, double* dg,
                                double* growth, hipStream_t st) {
   if (B <= 0) return hipSuccess;
+  struct Mark {
+    hipStream_t s;
+    explicit Mark(hipStream_t s_) : s(s_) { mark_begin(K_SMALL, s); }
+    ~Mark() { mark_end(K_SMALL, s); }
+  } mark(st);
   if (N <= 16) {
     hipLaunchKernelGGL((small_factor_kernel<16, 64>), dim3(B), dim3(64), 0, st,
                        descs, hbuf, N, L, lad, dg, growth);

@@ -19,6 +19,7 @@
 #include "../../include/sca.h"
 #include "sca_common.h"
 #include "sca_kernels.h"
+#include "sca_profile.h"
 #include "sca_runtime.h"
 
 namespace {
@@ -52,6 +53,7 @@ struct sca_ctx {
   size_t ws_bytes = 0;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  sca::Profiler prof;
 };
 
 namespace sca {
@@ -134,13 +136,28 @@ sca_status ensure_pinned(sca_ctx* ctx, size_t bytes) {
   return SCA_OK;
 }
 
+// Per-call scope: selects the context's device and installs its profiler
+// for the launches of this call; pending kernel timings are folded in when
+// the call ends (every call drains its stream before returning).
 struct DeviceGuard {
   int prev = -1;
+  sca_ctx* ctx = nullptr;
   explicit DeviceGuard(int dev) {
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (prev != dev) (void)hipSetDevice(dev);
   }
+  DeviceGuard(sca_ctx* c, int dev) : DeviceGuard(dev) {
+    ctx = c;
+    current_profiler() = &c->prof;
+  }
   ~DeviceGuard() {
+    if (ctx) {
+      current_profiler() = nullptr;
+      if (ctx->prof.on) {
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->prof.resolve();
+      }
+    }
     if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
@@ -308,7 +325,7 @@ sca_status sca_create(int device, void* hip_stream, size_t hbm_budget_bytes,
 
 void sca_destroy(sca_ctx* ctx) {
   if (!ctx) return;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx, ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -326,7 +343,7 @@ sca_status sca_potential(sca_ctx* ctx, const sca_params* p, const double* phi,
                          double* omega2) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, omega2, "omega2"))) return s;
   return eval_single(ctx, p, phi, nullptr, omega2, nullptr);
@@ -336,7 +353,7 @@ sca_status sca_grad(sca_ctx* ctx, const sca_params* p, const double* phi,
                     double* grad, double* omega2) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
   if ((s = check_dev_ptr(ctx, omega2, "omega2", true))) return s;
@@ -350,13 +367,15 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
   if (s) return s;
   if (!o) return fail(SCA_EINVAL, "opts is NULL");
   if (!res) return fail(SCA_EINVAL, "result is NULL");
-  if (o->n_steps < 0 || o->check_every < 0 || o->t0 < 0 || o->reserved != 0)
+  if (o->n_steps < 0 || o->check_every < 0 || o->t0 < 0)
     return fail(SCA_EINVAL, "n_steps, check_every, t0 must be >= 0");
+  if (o->flags & ~SCA_ADAM_NO_FINAL_EVAL)
+    return fail(SCA_EINVAL, "unknown ADAM flags 0x%x", o->flags);
   if (!(o->lr > 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) ||
       !(o->beta2 >= 0.0 && o->beta2 < 1.0) || !(o->eps >= 0.0) ||
       !(o->grad_tol >= 0.0))
     return fail(SCA_EINVAL, "invalid ADAM hyper-parameters");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, m, "m"))) return s;
   if ((s = check_dev_ptr(ctx, v, "v"))) return s;
@@ -391,11 +410,16 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
       }
     }
   }
-  // statistics at the returned phi
-  s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, 0, hy, done == 0);
-  if (s) return s;
   ProbStats S;
-  if ((s = read_stats(ctx, c, 1, &S))) return s;
+  if (o->flags & SCA_ADAM_NO_FINAL_EVAL) {
+    // statistics of the last evaluated phi (input of the final update)
+    if ((s = read_stats(ctx, c, 1, &S))) return s;
+  } else {
+    // statistics at the returned phi
+    s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, 0, hy, done == 0);
+    if (s) return s;
+    if ((s = read_stats(ctx, c, 1, &S))) return s;
+  }
   res->omega = S.omega;
   res->omega_tilde = S.omega_tilde;
   res->af_order = S.af_order;
@@ -417,7 +441,7 @@ sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
   if (s) return s;
   if (n_z < 1 || n_z > kMaxShifts)
     return fail(SCA_EINVAL, "n_z=%d: must be in [1, %d]", n_z, kMaxShifts);
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, z, "z"))) return s;
   if ((s = check_dev_ptr(ctx, logabsdet, "logabsdet"))) return s;
@@ -449,7 +473,7 @@ sca_status sca_dos(sca_ctx* ctx, const sca_params* p, const double* phi,
     return fail(SCA_EINVAL, "n_w=%d: must be in [1, %d]", n_w, kMaxShifts);
   if (!(eta > 0.0) || !std::isfinite(eta))
     return fail(SCA_EINVAL, "eta=%g: must be finite and > 0", eta);
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, w, "w"))) return s;
   if ((s = check_dev_ptr(ctx, rho, "rho"))) return s;
@@ -489,7 +513,7 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
                          void* factors, double* omega2) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
   if ((s = check_dev_ptr(ctx, omega2, "omega2"))) return s;
@@ -527,7 +551,7 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
                                  double* grad) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
   if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
@@ -548,6 +572,32 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
   ProbStats S;
   if ((s = read_stats(ctx, c, 1, &S))) return s;
   if (S.nonfinite) return fail(SCA_ENUMERIC, "non-finite gradient");
+  return SCA_OK;
+}
+
+sca_status sca_profile(sca_ctx* ctx, int enable) {
+  g_err.clear();
+  if (!ctx) return fail(SCA_EINVAL, "context is NULL");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->prof.resolve();
+  if (enable) ctx->prof.reset();
+  ctx->prof.on = enable != 0;
+  return SCA_OK;
+}
+
+sca_status sca_profile_read(sca_ctx* ctx, double* total_ms,
+                            int64_t* launches) {
+  g_err.clear();
+  if (!ctx) return fail(SCA_EINVAL, "context is NULL");
+  if (!total_ms || !launches) return fail(SCA_EINVAL, "output is NULL");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->prof.resolve();
+  for (int k = 0; k < SCA_PROFILE_SLOTS; ++k) {
+    total_ms[k] = ctx->prof.total_ms[k];
+    launches[k] = ctx->prof.launches[k];
+  }
   return SCA_OK;
 }
 

@@ -1,6 +1,8 @@
 // Factorisation path selection.
 //   N <= 64  : fused small kernel (matrix in LDS), FP64 for both precisions
 //              (these matrices are too small for the FP32 route to pay).
+//   N <= 1024: blocked FP64 path (LU, then U^-1 / L^-1, then the diagonal).
+#include "sca_blocked.h"
 #include "sca_common.h"
 #include "sca_kernels.h"
 #include "sca_runtime.h"
@@ -13,30 +15,56 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
 bool path_supported(int N, int precision) {
-  (void)precision;
-  return N >= 1 && N <= kSmallMax;
+  if (N < 1) return false;
+  if (N <= kSmallMax) return true;
+  if (precision == 0) return blocked_plan_f64(N).cfg >= 0;
+  return false;
 }
 
 size_t factor_workspace_bytes(int N, int B, int precision) {
-  (void)B; (void)precision;
+  (void)precision;
   if (N <= kSmallMax) return 0;
-  return 0;
+  return blocked_factor_bytes_f64(blocked_plan_f64(N), B);
 }
+
+namespace {
+
+struct BlockedBufs { double* F; int* perm; double* tri; };
+
+BlockedBufs carve_blocked(void* fact, const BlockedPlan& p, int B) {
+  char* c = static_cast<char*>(fact);
+  BlockedBufs r;
+  r.F = reinterpret_cast<double*>(c);
+  c += align256(sizeof(double) * 2 * (size_t)B * p.Np * p.Np);
+  r.perm = reinterpret_cast<int*>(c);
+  c += align256(sizeof(int) * (size_t)B * p.Np);
+  r.tri = reinterpret_cast<double*>(c);
+  return r;
+}
+
+}  // namespace
 
 hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
                         int L, int precision, double* lad, double* dg,
                         double* growth, void* fact, hipStream_t st) {
-  (void)precision; (void)fact;
+  (void)precision;
+  if (B <= 0) return hipSuccess;
   if (N <= kSmallMax)
     return launch_small_factor(descs, hbuf, B, N, L, lad, dg, growth, st);
-  return hipErrorInvalidValue;
+  const BlockedPlan p = blocked_plan_f64(N);
+  if (p.cfg < 0) return hipErrorInvalidValue;
+  BlockedBufs bb = carve_blocked(fact, p, B);
+  hipError_t e = blocked_lu_f64(p, descs, hbuf, B, N, L, bb.F, bb.perm, bb.tri,
+                                lad, growth, st);
+  if (e != hipSuccess) return e;
+  return blocked_inv_f64(p, B, N, bb.F, bb.perm, bb.tri, dg, st);
 }
 
 size_t autograd_factor_bytes(int N, int B, int precision) {
-  (void)precision;
   size_t bytes = align256(sizeof(double) * (size_t)B)        // lad
                + align256(sizeof(double) * (size_t)B)        // growth
-               + align256(sizeof(double) * 2 * (size_t)B * N);  // dg
+               + align256(sizeof(double) * 2 * (size_t)B * N)  // dg
+               + factor_workspace_bytes(N, B, precision);   // LU factors
   return bytes;
 }
 
@@ -50,7 +78,7 @@ AutogradLayout autograd_layout(void* base, int N, int B, int precision) {
   p += align256(sizeof(double) * (size_t)B);
   a.dg = reinterpret_cast<double*>(p);
   p += align256(sizeof(double) * 2 * (size_t)B * N);
-  a.fact = nullptr;
+  a.fact = factor_workspace_bytes(N, B, precision) ? p : nullptr;
   return a;
 }
 
@@ -58,15 +86,24 @@ hipError_t factor_forward(const MatDesc* descs, const double* hbuf, int B,
                           int N, int L, int precision, double* lad, double* dg,
                           double* growth, void* fact, hipStream_t st) {
   // the small path forms diag(A^-1) in the same pass as the LU
-  return factor_batch(descs, hbuf, B, N, L, precision, lad, dg, growth, fact,
-                      st);
+  if (N <= kSmallMax)
+    return factor_batch(descs, hbuf, B, N, L, precision, lad, dg, growth, fact,
+                        st);
+  const BlockedPlan p = blocked_plan_f64(N);
+  if (p.cfg < 0) return hipErrorInvalidValue;
+  BlockedBufs bb = carve_blocked(fact, p, B);
+  return blocked_lu_f64(p, descs, hbuf, B, N, L, bb.F, bb.perm, bb.tri, lad,
+                        growth, st);
 }
 
 hipError_t factor_backward(int B, int N, int precision, const double* lad,
                            double* dg, void* fact, hipStream_t st) {
-  (void)B; (void)lad; (void)dg; (void)fact; (void)st; (void)precision;
+  (void)lad; (void)precision;
   if (N <= kSmallMax) return hipSuccess;   // dg already complete
-  return hipErrorInvalidValue;
+  const BlockedPlan p = blocked_plan_f64(N);
+  if (p.cfg < 0) return hipErrorInvalidValue;
+  BlockedBufs bb = carve_blocked(fact, p, B);
+  return blocked_inv_f64(p, B, N, bb.F, bb.perm, bb.tri, dg, st);
 }
 
 __global__ void make_shifts_kernel(const double* __restrict__ w, int n_w,

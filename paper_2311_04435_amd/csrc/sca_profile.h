@@ -1,0 +1,50 @@
+// Per-kernel timing with HIP events on the launching stream.  The API layer
+// installs a Profiler for the duration of a call on the calling thread; the
+// launch sites bracket each kernel with mark_begin / mark_end.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <vector>
+
+namespace sca {
+
+enum KernelClass {
+  K_SMALL = 0,    // fused small-lattice factor + inverse
+  K_LU = 1,       // blocked LU
+  K_TRTRI = 2,    // blocked U^-1 / L^-1
+  K_DIAGDOT = 3,  // diagonal of the inverse from U^-1, L^-1
+  K_REDUCE = 4,   // Matsubara/spin reduction + ADAM
+  K_SETUP = 5,    // descriptors and diagonal vectors
+  K_REFINE = 6,   // FP64 refinement of the FP32 route
+  K_COUNT = 8
+};
+
+struct Profiler {
+  bool on = false;
+  double total_ms[K_COUNT] = {};
+  long long launches[K_COUNT] = {};
+  struct Pending { int k; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+
+  hipEvent_t get();
+  void begin(int k, hipStream_t st);
+  void end(int k, hipStream_t st);
+  // after the stream has drained: fold pending events into the totals
+  void resolve();
+  void reset();
+  void release();
+};
+
+// Profiler of the current call on this thread (nullptr: not timing).
+Profiler*& current_profiler();
+
+inline void mark_begin(int k, hipStream_t st) {
+  Profiler* p = current_profiler();
+  if (p && p->on) p->begin(k, st);
+}
+inline void mark_end(int k, hipStream_t st) {
+  Profiler* p = current_profiler();
+  if (p && p->on) p->end(k, st);
+}
+
+}  // namespace sca

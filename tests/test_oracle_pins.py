@@ -112,6 +112,18 @@ def test_eigenvalue_identity(L, delta):
         assert np.max(np.abs(lad - ref)) < 1e-12
 
 
+@pytest.mark.parametrize("L", [4, 6])
+def test_shifted_terms_route_s_equals_route_d(L):
+    phi = uniform(13, L * L, -0.5, 0.5)
+    p = P(L, delta=0.7)
+    z = np.array([0.3j, 2.9j, 0.4 + 0.05j, -3.0 + 0.2j])
+    for spin in (1, -1):
+        a, da = oracle.shifted_terms(p, phi, z, spin)
+        b, db = oracle.shifted_terms_s(p, phi, z, spin)
+        assert np.max(np.abs(a - b)) < 1e-12
+        assert np.max(np.abs(da - db)) < 1e-12 * np.max(np.abs(da))
+
+
 @pytest.mark.parametrize("L,delta,U", [(4, 0.0, 4.0), (4, 1.2, 6.0), (6, 0.4, 3.0)])
 def test_route_d_equals_route_s(L, delta, U):
     phi = uniform(5, L * L, -0.5, 0.5)
