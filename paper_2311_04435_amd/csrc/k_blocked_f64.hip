@@ -49,14 +49,15 @@ __device__ inline void argmax_wave(double& mag, int& row) {
 template <int NB>
 struct LuLds {
   int* perm;          // [Np] position -> original row
-  double* cmag;       // [2][WAVES]
-  int* crowi;         // [2][WAVES]
-  double *rAr, *rAi;  // [NB] row at the pivot position before the swap
-  double *rBr, *rBi;  // [NB] pivot row
+  double* cmag;       // [2][WAVES] best |Re|+|Im| of each wave (by column parity)
+  int* crowi;         // [2][WAVES] its position
+  double *rAr, *rAi;  // [2][NB] row at the pivot position before the swap
+  double *slr, *sli;  // [2][WAVES][NB] each wave's candidate pivot row
   double *mr, *mi;    // [Np] multipliers of the current column
   double *xsr, *xsi;  // [NB][NB+1] rows of a previous panel / diagonal block
   double *lsr, *lsi;  // [NB][NB+1] L_II^-1
   double *unr, *uni;  // [NB][NB+1] -U_IJ, or U_JJ^-1
+  double *tr_, *ti_;  // [NB*NB/2] scratch of the block inversion
 };
 
 constexpr int LD(int NB) { return NB + 1; }
@@ -67,11 +68,138 @@ size_t lu_lds_bytes(int Np, int NB, int waves) {
   size_t b = 0;
   b += sizeof(int) * Np;
   b += sizeof(double) * 2 * waves + sizeof(int) * 2 * waves;
-  b += sizeof(double) * 4 * NB;
+  b += sizeof(double) * 4 * NB;                 // rA [2][NB] re, im
+  b += sizeof(double) * 4 * waves * NB;         // slots [2][W][NB] re, im
   b += sizeof(double) * 2 * Np;
   b += sizeof(double) * 6 * NB * (NB + 1);
+  b += sizeof(double) * NB * NB;                // inversion scratch
   return b + 64;
 }
+
+namespace {
+
+__device__ inline double readlane_d(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inverses of the unit lower and the upper triangle of the NB x NB block
+// (xr, xi; leading dimension NB+1), by recursive doubling: 4x4 leaves by
+// one thread each, then for s = 8, 16, .. NB
+//   [A 0; C D]^-1 = [A^-1 0; -D^-1 C A^-1  D^-1]
+//   [A B; 0 D]^-1 = [A^-1  -A^-1 B D^-1; 0 D^-1]
+// with the products spread over all threads.  Outputs carry explicit zeros
+// and the unit diagonal of L^-1.
+template <int NB, int NT>
+__device__ void block_tri_inverses(const double* xr, const double* xi,
+                                   double* lr, double* li, double* ur,
+                                   double* ui, double* tr, double* ti,
+                                   int tid) {
+  constexpr int LDB = NB + 1;
+  for (int e = tid; e < NB * NB; e += NT) {
+    const int r = e / NB, c = e % NB;
+    lr[r * LDB + c] = 0.0; li[r * LDB + c] = 0.0;
+    ur[r * LDB + c] = 0.0; ui[r * LDB + c] = 0.0;
+  }
+  __syncthreads();
+  constexpr int NLEAF = NB / 4;
+  if (tid < 2 * NLEAF) {
+    const int o = 4 * (tid % NLEAF);
+    if (tid < NLEAF) {
+      for (int c = 0; c < 4; ++c) {
+        lr[(o + c) * LDB + o + c] = 1.0;
+        for (int r = c + 1; r < 4; ++r) {
+          double sr = xr[(o + r) * LDB + o + c], si = xi[(o + r) * LDB + o + c];
+          for (int k = c + 1; k < r; ++k) {
+            const double ar = xr[(o + r) * LDB + o + k], ai = xi[(o + r) * LDB + o + k];
+            const double br = lr[(o + k) * LDB + o + c], bi = li[(o + k) * LDB + o + c];
+            sr += ar * br - ai * bi;
+            si += ar * bi + ai * br;
+          }
+          lr[(o + r) * LDB + o + c] = -sr;
+          li[(o + r) * LDB + o + c] = -si;
+        }
+      }
+    } else {
+      for (int c = 0; c < 4; ++c) {
+        for (int r = c; r >= 0; --r) {
+          double sr = (r == c) ? 1.0 : 0.0, si = 0.0;
+          for (int k = r + 1; k <= c; ++k) {
+            const double ar = xr[(o + r) * LDB + o + k], ai = xi[(o + r) * LDB + o + k];
+            const double br = ur[(o + k) * LDB + o + c], bi = ui[(o + k) * LDB + o + c];
+            sr -= ar * br - ai * bi;
+            si -= ar * bi + ai * br;
+          }
+          const double pr = xr[(o + r) * LDB + o + r], pi = xi[(o + r) * LDB + o + r];
+          const double d = pr * pr + pi * pi;
+          ur[(o + r) * LDB + o + c] = (sr * pr + si * pi) / d;
+          ui[(o + r) * LDB + o + c] = (si * pr - sr * pi) / d;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int sz = 8; sz <= NB; sz *= 2) {
+    const int h = sz / 2, npair = NB / sz, per = npair * h * h;
+    // T = C A^-1 (lower) and T = A^-1 B (upper), h x h per pair
+    for (int e = tid; e < 2 * per; e += NT) {
+      const int up = e >= per, rest = e - up * per;
+      const int pr_ = rest / (h * h), r = (rest / h) % h, c = rest % h;
+      const int o = pr_ * sz;
+      double sr = 0.0, si = 0.0;
+      if (!up) {
+        for (int k = c; k < h; ++k) {   // C[r][k] A^-1[k][c], A^-1 lower
+          const double ar = xr[(o + h + r) * LDB + o + k], ai = xi[(o + h + r) * LDB + o + k];
+          const double br = lr[(o + k) * LDB + o + c], bi = li[(o + k) * LDB + o + c];
+          sr += ar * br - ai * bi;
+          si += ar * bi + ai * br;
+        }
+      } else {
+        for (int k = r; k < h; ++k) {   // A^-1[r][k] B[k][c], A^-1 upper
+          const double ar = ur[(o + r) * LDB + o + k], ai = ui[(o + r) * LDB + o + k];
+          const double br = xr[(o + k) * LDB + o + h + c], bi = xi[(o + k) * LDB + o + h + c];
+          sr += ar * br - ai * bi;
+          si += ar * bi + ai * br;
+        }
+      }
+      tr[e] = sr;
+      ti[e] = si;
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * per; e += NT) {
+      const int up = e >= per, rest = e - up * per;
+      const int pr_ = rest / (h * h), r = (rest / h) % h, c = rest % h;
+      const int o = pr_ * sz;
+      const double* Tr = tr + up * per + pr_ * h * h;
+      const double* Ti = ti + up * per + pr_ * h * h;
+      double sr = 0.0, si = 0.0;
+      if (!up) {
+        for (int k = 0; k <= r; ++k) {   // -D^-1[r][k] T[k][c], D^-1 lower
+          const double ar = lr[(o + h + r) * LDB + o + h + k], ai = li[(o + h + r) * LDB + o + h + k];
+          const double br = Tr[k * h + c], bi = Ti[k * h + c];
+          sr += ar * br - ai * bi;
+          si += ar * bi + ai * br;
+        }
+        lr[(o + h + r) * LDB + o + c] = -sr;
+        li[(o + h + r) * LDB + o + c] = -si;
+      } else {
+        for (int k = 0; k <= c; ++k) {   // -T[r][k] D^-1[k][c], D^-1 upper
+          const double ar = Tr[r * h + k], ai = Ti[r * h + k];
+          const double br = ur[(o + h + k) * LDB + o + h + c], bi = ui[(o + h + k) * LDB + o + h + c];
+          sr += ar * br - ai * bi;
+          si += ar * bi + ai * br;
+        }
+        ur[(o + r) * LDB + o + h + c] = -sr;
+        ui[(o + r) * LDB + o + h + c] = -si;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
 
 template <int WAVES, int RT, int CT>
 __global__ void __launch_bounds__(WAVES * 64)
@@ -94,10 +222,12 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   {
     double* d = lds_raw;
     S.mr = d; d += Np; S.mi = d; d += Np;
-    S.rAr = d; d += NB; S.rAi = d; d += NB; S.rBr = d; d += NB; S.rBi = d; d += NB;
+    S.rAr = d; d += 2 * NB; S.rAi = d; d += 2 * NB;
+    S.slr = d; d += 2 * WAVES * NB; S.sli = d; d += 2 * WAVES * NB;
     S.xsr = d; d += NB * LD(NB); S.xsi = d; d += NB * LD(NB);
     S.lsr = d; d += NB * LD(NB); S.lsi = d; d += NB * LD(NB);
     S.unr = d; d += NB * LD(NB); S.uni = d; d += NB * LD(NB);
+    S.tr_ = d; d += NB * NB / 2; S.ti_ = d; d += NB * NB / 2;
     S.cmag = d; d += 2 * WAVES;
     int* ip = reinterpret_cast<int*>(d);
     S.crowi = ip; ip += 2 * WAVES;
@@ -202,24 +332,21 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           dst[(16 * rt + crow(g, i)) * LD(NB) + 16 * ct + q] = -acc[i];
       }
       __syncthreads();
-      // (c) panel-I rows become U_IJ; rows below get X += L[:, I] (-U_IJ)
+      // (c) U_IJ is final: all threads copy it from LDS to its rows of F (the
+      //     register copies of rows above the panel are not used again);
+      //     rows below panel I get X += L[:, I] (-U_IJ)
+      for (int e = tid; e < NB * NB; e += NT) {
+        const int rr = e / NB, cc = e % NB;
+        const double ur = -S.unr[rr * LD(NB) + cc], ui = -S.uni[rr * LD(NB) + cc];
+        const size_t o = (size_t)S.perm[r0 + rr] * Np + c0 + cc;
+        Fr[o] = ur;
+        Fi[o] = ui;
+        umax = fmax(umax, fabs(ur) + fabs(ui));
+      }
 #pragma unroll
       for (int s = 0; s < RT; ++s) {
         const int t = w + WAVES * s;
-        if (t >= (r0 >> 4) && t < ((r0 + NB) >> 4)) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int pr = 16 * t + crow(g, i) - r0;
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-              const double ur = -S.unr[pr * LD(NB) + 16 * ct + q];
-              const double ui = -S.uni[pr * LD(NB) + 16 * ct + q];
-              xr[s][ct][i] = ur;
-              xi[s][ct][i] = ui;
-              umax = fmax(umax, fabs(ur) + fabs(ui));
-            }
-          }
-        } else if (t < ntiles && 16 * t >= r0 + NB) {
+        if (t < ntiles && 16 * t >= r0 + NB) {
           // A operand: L[16t + q][r0 + KPL g + ks] read from original row
           const int ra = S.perm[16 * t + q];
           const double* pa_r = Fr + (size_t)ra * Np + r0 + KPL * g;
@@ -247,14 +374,24 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       }
     }
 
-    // ---- 3. panel factorisation of positions >= c0, column by column ------
+    // ---- 3. panel factorisation of positions >= c0, one barrier per column
+    // Each wave finds its best candidate row for column j and publishes it
+    // (|Re|+|Im|, position and the row's values) together with the row now
+    // at the pivot position; after the barrier every lane picks the winner
+    // (largest magnitude, lowest position on ties) and reads the pivot row
+    // from LDS.  Multipliers go from the lane owning column j to the other
+    // lanes of its row group through LDS inside the wave (no barrier).
 #pragma unroll
     for (int cj = 0; cj < CT; ++cj) {
       for (int qj = 0; qj < 16; ++qj) {
         const int j = 16 * cj + qj;
         const int pj = c0 + j;
         const int par = j & 1;
-        // A: pivot candidates (largest |Re|+|Im|, lowest position on ties)
+        double* slr = S.slr + par * WAVES * NB;
+        double* sli = S.sli + par * WAVES * NB;
+        double* rar = S.rAr + par * NB;
+        double* rai = S.rAi + par * NB;
+        // A: wave candidate
         double best = -1.0;
         int brow = 0x7fffffff;
         if (q == qj) {
@@ -271,69 +408,78 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
             }
           }
         }
-        argmax_wave(best, brow);
-        if (lane == 0) { S.cmag[par * WAVES + w] = best; S.crowi[par * WAVES + w] = brow; }
-        __syncthreads();
-        // B: choose the pivot; owners publish the two rows to swap
-        double bm = -1.0;
-        int piv = 0x7fffffff;
+        double wbest = readlane_d(best, qj);
+        int wrow = __builtin_amdgcn_readlane(brow, qj);
 #pragma unroll
-        for (int ww = 0; ww < WAVES; ++ww) {
-          const double m = S.cmag[par * WAVES + ww];
-          const int rr = S.crowi[par * WAVES + ww];
-          if (m > bm || (m == bm && rr < piv)) { bm = m; piv = rr; }
+        for (int gg = 1; gg < 4; ++gg) {
+          const double m = readlane_d(best, qj + 16 * gg);
+          const int rr = __builtin_amdgcn_readlane(brow, qj + 16 * gg);
+          if (m > wbest || (m == wbest && rr < wrow)) { wbest = m; wrow = rr; }
         }
-        if (piv >= Np) piv = pj;   // no comparable entry (NaN column)
+        if (lane == 0) { S.cmag[par * WAVES + w] = wbest; S.crowi[par * WAVES + w] = wrow; }
 #pragma unroll
         for (int s = 0; s < RT; ++s) {
           const int t = w + WAVES * s;
+          if (t < ntiles && 16 * t + 15 >= pj) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int p = 16 * t + crow(g, i);
-            if (t < ntiles && p == piv) {
+            for (int i = 0; i < 4; ++i) {
+              const int p = 16 * t + crow(g, i);
+              if (p == wrow) {
 #pragma unroll
-              for (int ct = 0; ct < CT; ++ct) {
-                S.rBr[16 * ct + q] = xr[s][ct][i];
-                S.rBi[16 * ct + q] = xi[s][ct][i];
+                for (int ct = 0; ct < CT; ++ct) {
+                  slr[w * NB + 16 * ct + q] = xr[s][ct][i];
+                  sli[w * NB + 16 * ct + q] = xi[s][ct][i];
+                }
               }
-            }
-            if (t < ntiles && p == pj) {
+              if (p == pj) {
 #pragma unroll
-              for (int ct = 0; ct < CT; ++ct) {
-                S.rAr[16 * ct + q] = xr[s][ct][i];
-                S.rAi[16 * ct + q] = xi[s][ct][i];
+                for (int ct = 0; ct < CT; ++ct) {
+                  rar[16 * ct + q] = xr[s][ct][i];
+                  rai[16 * ct + q] = xi[s][ct][i];
+                }
               }
             }
           }
         }
-        if (tid == 0 && piv != pj) {
-          const int tp = S.perm[pj];
-          S.perm[pj] = S.perm[piv];
-          S.perm[piv] = tp;
-        }
         __syncthreads();
-        // C: swap, scale the column below the pivot into multipliers
-        const double pvr = S.rBr[j], pvi = S.rBi[j];
-        const double den = pvr * pvr + pvi * pvi;
-        const double ivr = pvr / den, ivi = -pvi / den;
+        // B: the winner and its row
+        double bm = -1.0;
+        int piv = 0x7fffffff, wwin = 0;
+#pragma unroll
+        for (int ww = 0; ww < WAVES; ++ww) {
+          const double m = S.cmag[par * WAVES + ww];
+          const int rr = S.crowi[par * WAVES + ww];
+          if (m > bm || (m == bm && rr < piv)) { bm = m; piv = rr; wwin = ww; }
+        }
+        const double* pvr_s = slr + wwin * NB;
+        const double* pvi_s = sli + wwin * NB;
+        if (piv >= Np) {   // no comparable entry (NaN column): keep row pj
+          piv = pj;
+          pvr_s = rar;
+          pvi_s = rai;
+        }
+        double prr[CT], pri[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) { prr[ct] = pvr_s[16 * ct + q]; pri[ct] = pvi_s[16 * ct + q]; }
+        const double pvr = pvr_s[j], pvi = pvi_s[j];
+        const double rden = 1.0 / (pvr * pvr + pvi * pvi);
+        const double ivr = pvr * rden, ivi = -pvi * rden;
+        // C: swap; multipliers below the pivot (owner lanes of column j)
 #pragma unroll
         for (int s = 0; s < RT; ++s) {
           const int t = w + WAVES * s;
-          if (t < ntiles) {
+          if (t < ntiles && 16 * t + 15 >= pj) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int p = 16 * t + crow(g, i);
               if (piv != pj && p == pj) {
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
-                  xr[s][ct][i] = S.rBr[16 * ct + q];
-                  xi[s][ct][i] = S.rBi[16 * ct + q];
-                }
+                for (int ct = 0; ct < CT; ++ct) { xr[s][ct][i] = prr[ct]; xi[s][ct][i] = pri[ct]; }
               } else if (piv != pj && p == piv) {
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
-                  xr[s][ct][i] = S.rAr[16 * ct + q];
-                  xi[s][ct][i] = S.rAi[16 * ct + q];
+                  xr[s][ct][i] = rar[16 * ct + q];
+                  xi[s][ct][i] = rai[16 * ct + q];
                 }
               }
               if (q == qj && p > pj) {
@@ -348,9 +494,17 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
             }
           }
         }
-        if (tid == 0) lsum += log(hypot(pvr, pvi));
-        if (tid >= j && tid < NB) umax = fmax(umax, fabs(S.rBr[tid]) + fabs(S.rBi[tid]));
-        __syncthreads();
+        if (tid == 0) {
+          if (piv != pj) {
+            const int tp = S.perm[pj];
+            S.perm[pj] = S.perm[piv];
+            S.perm[piv] = tp;
+          }
+        }
+        if (tid >= j && tid < NB) umax = fmax(umax, fabs(pvr_s[tid]) + fabs(pvi_s[tid]));
+        // the multipliers of this wave's rows were written by this wave
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         // D: rank-1 update of the columns right of j, rows below pj
 #pragma unroll
         for (int s = 0; s < RT; ++s) {
@@ -364,9 +518,8 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
                   if (16 * ct + q > j) {
-                    const double ur = S.rBr[16 * ct + q], ui = S.rBi[16 * ct + q];
-                    xr[s][ct][i] -= lr * ur - li * ui;
-                    xi[s][ct][i] -= lr * ui + li * ur;
+                    xr[s][ct][i] -= lr * prr[ct] - li * pri[ct];
+                    xi[s][ct][i] -= lr * pri[ct] + li * prr[ct];
                   }
                 }
               }
@@ -376,7 +529,8 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       }
     }
 
-    // ---- 4. inverses of the diagonal blocks L_JJ (unit) and U_JJ ---------
+    // ---- 4. diagonal block to LDS (inverted after the store, when the
+    //         block column registers are free)
 #pragma unroll
     for (int s = 0; s < RT; ++s) {
       const int t = w + WAVES * s;
@@ -392,50 +546,26 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         }
       }
     }
-    __syncthreads();
-    if (tid < NB) {
-      // column c of L_JJ^-1: Y[r][c] = -sum_{k=c}^{r-1} L[r][k] Y[k][c]
-      const int c = tid;
-      for (int r = 0; r < NB; ++r) {
-        double yr, yi;
-        if (r < c) { yr = 0.0; yi = 0.0; }
-        else if (r == c) { yr = 1.0; yi = 0.0; }
-        else {
-          double sr = S.xsr[r * LD(NB) + c], si = S.xsi[r * LD(NB) + c];
-          for (int k = c + 1; k < r; ++k) {
-            const double lr = S.xsr[r * LD(NB) + k], li = S.xsi[r * LD(NB) + k];
-            const double vr = S.lsr[k * LD(NB) + c], vi = S.lsi[k * LD(NB) + c];
-            sr += lr * vr - li * vi;
-            si += lr * vi + li * vr;
+    // ---- 5. store rows >= c0 of block column J at the original rows -------
+#pragma unroll
+    for (int s = 0; s < RT; ++s) {
+      const int t = w + WAVES * s;
+      if (t < ntiles && 16 * t >= c0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = S.perm[16 * t + crow(g, i)];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            Fr[(size_t)r * Np + c0 + 16 * ct + q] = xr[s][ct][i];
+            Fi[(size_t)r * Np + c0 + 16 * ct + q] = xi[s][ct][i];
           }
-          yr = -sr; yi = -si;
         }
-        S.lsr[r * LD(NB) + c] = yr;
-        S.lsi[r * LD(NB) + c] = yi;
-      }
-    } else if (tid < 2 * NB) {
-      // column c of U_JJ^-1: Z[r][c] = -(sum_{k=r+1}^{c} U[r][k] Z[k][c]) / U[r][r]
-      const int c = tid - NB;
-      for (int r = NB - 1; r >= 0; --r) {
-        double zr = 0.0, zi = 0.0;
-        if (r <= c) {
-          double sr = (r == c) ? 1.0 : 0.0, si = 0.0;
-          for (int k = r + 1; k <= c; ++k) {
-            const double ur = S.xsr[r * LD(NB) + k], ui = S.xsi[r * LD(NB) + k];
-            const double vr = S.unr[k * LD(NB) + c], vi = S.uni[k * LD(NB) + c];
-            sr -= ur * vr - ui * vi;
-            si -= ur * vi + ui * vr;
-          }
-          const double pr = S.xsr[r * LD(NB) + r], pi = S.xsi[r * LD(NB) + r];
-          const double dd = pr * pr + pi * pi;
-          zr = (sr * pr + si * pi) / dd;
-          zi = (si * pr - sr * pi) / dd;
-        }
-        S.unr[r * LD(NB) + c] = zr;
-        S.uni[r * LD(NB) + c] = zi;
       }
     }
+    // ---- 6. inverses of the diagonal blocks L_JJ (unit) and U_JJ --------
     __syncthreads();
+    block_tri_inverses<NB, NT>(S.xsr, S.xsi, S.lsr, S.lsi, S.unr, S.uni,
+                               S.tr_, S.ti_, tid);
     {
       double* Lr = T + (size_t)(J * 4 + 0) * NB * NB;
       double* Li = Lr + NB * NB;
@@ -450,26 +580,16 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       }
     }
 
-    // ---- 5. store block column J at the original rows ---------------------
-#pragma unroll
-    for (int s = 0; s < RT; ++s) {
-      const int t = w + WAVES * s;
-      if (t < ntiles) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = S.perm[16 * t + crow(g, i)];
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            Fr[(size_t)r * Np + c0 + 16 * ct + q] = xr[s][ct][i];
-            Fi[(size_t)r * Np + c0 + 16 * ct + q] = xi[s][ct][i];
-          }
-        }
-      }
-    }
     __syncthreads();
   }
 
   for (int p = tid; p < Np; p += NT) perm_out[(size_t)b * Np + p] = S.perm[p];
+  // ln|det A| = sum_p ln|u_pp|, u_pp stored at row perm[p]; per-thread
+  // strided partial sums, then a fixed-order combination
+  for (int p = tid; p < Np; p += NT) {
+    const size_t e = (size_t)S.perm[p] * Np + p;
+    lsum += log(hypot(Fr[e], Fi[e]));
+  }
   // growth = max|u| / max|a| over the block
   for (int off = 32; off >= 1; off >>= 1) {
     umax = fmax(umax, __shfl_xor(umax, off));
@@ -477,12 +597,14 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   }
   __syncthreads();
   if (lane == 0) { S.mr[w] = umax; S.mi[w] = amax; }
+  S.slr[tid] = lsum;   // slot area: 4 WAVES NB >= NT doubles
   __syncthreads();
   if (tid == 0) {
-    double u = 0.0, a = 0.0;
+    double u = 0.0, a = 0.0, l = 0.0;
     for (int ww = 0; ww < WAVES; ++ww) { u = fmax(u, S.mr[ww]); a = fmax(a, S.mi[ww]); }
+    for (int k = 0; k < NT; ++k) l += S.slr[k];
     growth[b] = u / a;
-    lad[b] = lsum;
+    lad[b] = l;
   }
 }
 
@@ -770,18 +892,15 @@ hipError_t run_inv(int B, int N, int Np, double* F, const int* perm,
 }  // namespace
 
 BlockedPlan blocked_plan_f64(int N) {
+  // cfg 0: 4 waves x 4 row tiles (Np <= 256), cfg 1: 8 x 4 (Np <= 512), both
+  // with 32-wide blocks; cfg 2: 16-wide blocks for Np <= 1024 (LU on 16
+  // waves x 4 tiles, inverses on 8 x 8).
   BlockedPlan p{};
-  const int n16 = (N + 15) / 16 * 16;
-  if (n16 <= 256) { p.cfg = 0; p.NB = 32; }
-  else if (n16 <= 512) { p.cfg = 1; p.NB = 32; }
-  else if (n16 <= 1024) { p.cfg = 2; p.NB = 16; }
-  else { p.cfg = -1; p.NB = 0; return p; }
-  p.Np = (N + p.NB - 1) / p.NB * p.NB;
-  if ((p.cfg == 0 && p.Np > 256) || (p.cfg == 1 && p.Np > 512)) {
-    // rounding up to the block width crossed into the next configuration
-    p.cfg += 1;
-    if (p.cfg == 2) { p.NB = 16; p.Np = n16; }
-  }
+  const int n32 = (N + 31) / 32 * 32;
+  if (n32 <= 256) { p.cfg = 0; p.NB = 32; p.Np = n32; }
+  else if (n32 <= 512) { p.cfg = 1; p.NB = 32; p.Np = n32; }
+  else if (N <= 1024) { p.cfg = 2; p.NB = 16; p.Np = (N + 15) / 16 * 16; }
+  else { p.cfg = -1; p.NB = 0; p.Np = 0; }
   return p;
 }
 
@@ -792,7 +911,7 @@ hipError_t blocked_lu_f64(const BlockedPlan& p, const MatDesc* descs,
   switch (p.cfg) {
     case 0: return run_lu<4, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     case 1: return run_lu<8, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
-    case 2: return run_lu<8, 8, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 2: return run_lu<16, 4, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     default: return hipErrorInvalidValue;
   }
 }
