@@ -100,8 +100,12 @@ typedef struct {
   int32_t flags;        /* SCA_FLAG_* bits */
 } sca_result;
 
+/* SCA_FLAG_PIVOT_GROWTH: under SCA_FP32_REFINED a factorisation had pivot
+ * growth above 1e3; the steps after the check that saw it ran in FP64 when
+ * that path is built for N (sca_potential / sca_grad re-run in FP64 by
+ * themselves, or return SCA_ENUMERIC when it is not). */
 #define SCA_FLAG_NONFINITE 1    /* a non-finite value was produced */
-#define SCA_FLAG_PIVOT_GROWTH 2 /* FP32 growth above threshold: FP64 re-run */
+#define SCA_FLAG_PIVOT_GROWTH 2 /* FP32 growth above 1e3 (see above) */
 #define SCA_FLAG_CONVERGED 4    /* stopped by grad_tol */
 
 /* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`

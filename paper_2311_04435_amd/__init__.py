@@ -19,7 +19,9 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import SCAError, SCA_FP64, SCA_FP32_REFINED  # noqa: F401
+from ._lib import (SCAError, SCA_FP64, SCA_FP32_REFINED,  # noqa: F401
+                   SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH,
+                   SCA_FLAG_CONVERGED)
 
 PRECISIONS = {"fp64": SCA_FP64, "fp32r": SCA_FP32_REFINED}
 

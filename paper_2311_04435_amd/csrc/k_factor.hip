@@ -26,17 +26,26 @@
 
 namespace sca {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
 namespace {
 
-__device__ inline d4 mfma(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// f64 16x16x4 accumulator layout: lane l, element i holds row (l>>4) + 4 i,
-// column l & 15.
-__device__ inline int crow(int g, int i) { return g + 4 * i; }
+// MFMA of the element type: 16x16x4, A[m][k] from lane (k<<4 | m), B[k][n]
+// from lane (k<<4 | n); accumulator element i of lane (g<<4 | n) holds row
+// m(g, i) of column n (f64: g + 4i, f32: 4g + i, as measured on gfx950).
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int m(int g, int i) { return g + 4 * i; }
+};
+template <> struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int m(int g, int i) { return 4 * g + i; }
+};
 
 __device__ inline void argmax_wave(double& mag, int& row) {
   for (int off = 32; off >= 1; off >>= 1) {
@@ -46,34 +55,37 @@ __device__ inline void argmax_wave(double& mag, int& row) {
   }
 }
 
-template <int NB>
+template <typename T, int NB>
 struct LuLds {
   int* perm;          // [Np] position -> original row
   double* cmag;       // [2][WAVES] best |Re|+|Im| of each wave (by column parity)
   int* crowi;         // [2][WAVES] its position
-  double *rAr, *rAi;  // [2][NB] row at the pivot position before the swap
-  double *slr, *sli;  // [2][WAVES][NB] each wave's candidate pivot row
-  double *mr, *mi;    // [Np] multipliers of the current column
-  double *xsr, *xsi;  // [NB][NB+1] rows of a previous panel / diagonal block
-  double *lsr, *lsi;  // [NB][NB+1] L_II^-1
-  double *unr, *uni;  // [NB][NB+1] -U_IJ, or U_JJ^-1
-  double *tr_, *ti_;  // [NB*NB/2] scratch of the block inversion
+  T *rAr, *rAi;       // [2][NB] row at the pivot position before the swap
+  T *slr, *sli;       // [2][WAVES][NB] each wave's candidate pivot row
+  T *mr, *mi;         // [Np] multipliers of the current column
+  T *xsr, *xsi;       // [NB][NB+1] rows of a previous panel / diagonal block
+  T *lsr, *lsi;       // [NB][NB+1] L_II^-1
+  T *unr, *uni;       // [NB][NB+1] -U_IJ, or U_JJ^-1
+  T *tr_, *ti_;       // [NB*NB/2] scratch of the block inversion
+  double* red;        // [NT] final reductions
 };
 
 constexpr int LD(int NB) { return NB + 1; }
 
 }  // namespace
 
+template <typename T>
 size_t lu_lds_bytes(int Np, int NB, int waves) {
   size_t b = 0;
   b += sizeof(int) * Np;
   b += sizeof(double) * 2 * waves + sizeof(int) * 2 * waves;
-  b += sizeof(double) * 4 * NB;                 // rA [2][NB] re, im
-  b += sizeof(double) * 4 * waves * NB;         // slots [2][W][NB] re, im
-  b += sizeof(double) * 2 * Np;
-  b += sizeof(double) * 6 * NB * (NB + 1);
-  b += sizeof(double) * NB * NB;                // inversion scratch
-  return b + 64;
+  b += sizeof(double) * 64 * waves;        // final reductions
+  b += sizeof(T) * 4 * NB;                 // rA [2][NB] re, im
+  b += sizeof(T) * 4 * waves * NB;         // slots [2][W][NB] re, im
+  b += sizeof(T) * 2 * Np;
+  b += sizeof(T) * 6 * NB * (NB + 1);
+  b += sizeof(T) * NB * NB;                // inversion scratch
+  return b + 256;
 }
 
 namespace {
@@ -92,11 +104,9 @@ __device__ inline double readlane_d(double v, int lane) {
 //   [A B; 0 D]^-1 = [A^-1  -A^-1 B D^-1; 0 D^-1]
 // with the products spread over all threads.  Outputs carry explicit zeros
 // and the unit diagonal of L^-1.
-template <int NB, int NT>
-__device__ void block_tri_inverses(const double* xr, const double* xi,
-                                   double* lr, double* li, double* ur,
-                                   double* ui, double* tr, double* ti,
-                                   int tid) {
+template <typename T, int NB, int NT>
+__device__ void block_tri_inverses(const T* xr, const T* xi, T* lr, T* li,
+                                   T* ur, T* ui, T* tr, T* ti, int tid) {
   constexpr int LDB = NB + 1;
   for (int e = tid; e < NB * NB; e += NT) {
     const int r = e / NB, c = e % NB;
@@ -172,8 +182,8 @@ __device__ void block_tri_inverses(const double* xr, const double* xi,
       const int up = e >= per, rest = e - up * per;
       const int pr_ = rest / (h * h), r = (rest / h) % h, c = rest % h;
       const int o = pr_ * sz;
-      const double* Tr = tr + up * per + pr_ * h * h;
-      const double* Ti = ti + up * per + pr_ * h * h;
+      const T* Tr = tr + up * per + pr_ * h * h;
+      const T* Ti = ti + up * per + pr_ * h * h;
       double sr = 0.0, si = 0.0;
       if (!up) {
         for (int k = 0; k <= r; ++k) {   // -D^-1[r][k] T[k][c], D^-1 lower
@@ -201,12 +211,14 @@ __device__ void block_tri_inverses(const double* xr, const double* xi,
 
 }  // namespace
 
-template <int WAVES, int RT, int CT>
+template <typename T, int WAVES, int RT, int CT>
 __global__ void __launch_bounds__(WAVES * 64)
 lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
-          int N, int Np, int L, double* __restrict__ F,
-          int* __restrict__ perm_out, double* __restrict__ tri,
+          int N, int Np, int L, T* __restrict__ F,
+          int* __restrict__ perm_out, T* __restrict__ tri,
           double* __restrict__ lad, double* __restrict__ growth) {
+  typedef Mma<T> M;
+  typedef typename M::v4 V4;
   constexpr int NB = 16 * CT;
   constexpr int NT = WAVES * 64;
   constexpr int KPL = NB / 4;   // k values per lane group per panel
@@ -217,10 +229,13 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   const int ntiles = Np >> 4;
   const int nblk = Np / NB;
 
-  // carve LDS (doubles first for alignment)
-  LuLds<NB> S;
+  // carve LDS (doubles first, then T arrays, then ints)
+  LuLds<T, NB> S;
   {
-    double* d = lds_raw;
+    double* dd = lds_raw;
+    S.cmag = dd; dd += 2 * WAVES;
+    S.red = dd; dd += NT;
+    T* d = reinterpret_cast<T*>(dd);
     S.mr = d; d += Np; S.mi = d; d += Np;
     S.rAr = d; d += 2 * NB; S.rAi = d; d += 2 * NB;
     S.slr = d; d += 2 * WAVES * NB; S.sli = d; d += 2 * WAVES * NB;
@@ -228,7 +243,6 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     S.lsr = d; d += NB * LD(NB); S.lsi = d; d += NB * LD(NB);
     S.unr = d; d += NB * LD(NB); S.uni = d; d += NB * LD(NB);
     S.tr_ = d; d += NB * NB / 2; S.ti_ = d; d += NB * NB / 2;
-    S.cmag = d; d += 2 * WAVES;
     int* ip = reinterpret_cast<int*>(d);
     S.crowi = ip; ip += 2 * WAVES;
     S.perm = ip;
@@ -237,14 +251,14 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   const MatDesc dsc = descs[b];
   const double* h = hbuf + dsc.hoff;
   const size_t plane = (size_t)Np * Np;
-  double* Fr = F + (size_t)b * 2 * plane;
-  double* Fi = Fr + plane;
-  double* T = tri + (size_t)b * nblk * 4 * NB * NB;   // [nblk][2][2][NB][NB]
+  T* Fr = F + (size_t)b * 2 * plane;
+  T* Fi = Fr + plane;
+  T* Tb = tri + (size_t)b * nblk * 4 * NB * NB;   // [nblk][2][2][NB][NB]
 
   for (int p = tid; p < Np; p += NT) S.perm[p] = p;
   __syncthreads();
 
-  d4 xr[RT][CT], xi[RT][CT];
+  V4 xr[RT][CT], xi[RT][CT];
   double lsum = 0.0, umax = 0.0, amax = 0.0;
 
   for (int J = 0; J < nblk; ++J) {
@@ -255,7 +269,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       const int t = w + WAVES * s;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int p = 16 * t + crow(g, i);
+        const int p = 16 * t + M::m(g, i);
         const int r = (t < ntiles) ? S.perm[p] : Np;
         int n0 = -1, n1 = -1, n2 = -1, n3 = -1;
         double dre = 0.0;
@@ -278,8 +292,8 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           } else if (r == c) {
             re = 1.0;
           }
-          xr[s][ct][i] = re;
-          xi[s][ct][i] = im;
+          xr[s][ct][i] = T(re);
+          xi[s][ct][i] = T(im);
         }
       }
     }
@@ -294,7 +308,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         if (t >= (r0 >> 4) && t < ((r0 + NB) >> 4)) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int pr = 16 * t + crow(g, i) - r0;
+            const int pr = 16 * t + M::m(g, i) - r0;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
               S.xsr[pr * LD(NB) + 16 * ct + q] = xr[s][ct][i];
@@ -304,8 +318,8 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         }
       }
       {
-        const double* Lr = T + (size_t)(I * 4 + 0) * NB * NB;
-        const double* Li = Lr + NB * NB;
+        const T* Lr = Tb + (size_t)(I * 4 + 0) * NB * NB;
+        const T* Li = Lr + NB * NB;
         for (int e = tid; e < NB * NB; e += NT) {
           S.lsr[(e / NB) * LD(NB) + e % NB] = Lr[e];
           S.lsi[(e / NB) * LD(NB) + e % NB] = Li[e];
@@ -315,21 +329,21 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       // (b) un = -(L_II^-1 xs) = -U_IJ ; one 16x16 real output tile per task
       for (int task = w; task < 2 * CT * CT; task += WAVES) {
         const int rt = task / (2 * CT), ct = (task >> 1) % CT, part = task & 1;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        V4 acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int ks = 0; ks < NB / 4; ++ks) {
           const int k = 4 * ks + g;
-          const double ar = S.lsr[(16 * rt + q) * LD(NB) + k];
-          const double ai = S.lsi[(16 * rt + q) * LD(NB) + k];
-          const double br = S.xsr[k * LD(NB) + 16 * ct + q];
-          const double bi = S.xsi[k * LD(NB) + 16 * ct + q];
-          if (part == 0) { acc = mfma(ar, br, acc); acc = mfma(-ai, bi, acc); }
-          else { acc = mfma(ar, bi, acc); acc = mfma(ai, br, acc); }
+          const T ar = S.lsr[(16 * rt + q) * LD(NB) + k];
+          const T ai = S.lsi[(16 * rt + q) * LD(NB) + k];
+          const T br = S.xsr[k * LD(NB) + 16 * ct + q];
+          const T bi = S.xsi[k * LD(NB) + 16 * ct + q];
+          if (part == 0) { acc = M::mma(ar, br, acc); acc = M::mma(-ai, bi, acc); }
+          else { acc = M::mma(ar, bi, acc); acc = M::mma(ai, br, acc); }
         }
-        double* dst = part ? S.uni : S.unr;
+        T* dst = part ? S.uni : S.unr;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          dst[(16 * rt + crow(g, i)) * LD(NB) + 16 * ct + q] = -acc[i];
+          dst[(16 * rt + M::m(g, i)) * LD(NB) + 16 * ct + q] = -acc[i];
       }
       __syncthreads();
       // (c) U_IJ is final: all threads copy it from LDS to its rows of F (the
@@ -337,11 +351,11 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       //     rows below panel I get X += L[:, I] (-U_IJ)
       for (int e = tid; e < NB * NB; e += NT) {
         const int rr = e / NB, cc = e % NB;
-        const double ur = -S.unr[rr * LD(NB) + cc], ui = -S.uni[rr * LD(NB) + cc];
+        const T ur = -S.unr[rr * LD(NB) + cc], ui = -S.uni[rr * LD(NB) + cc];
         const size_t o = (size_t)S.perm[r0 + rr] * Np + c0 + cc;
         Fr[o] = ur;
         Fi[o] = ui;
-        umax = fmax(umax, fabs(ur) + fabs(ui));
+        umax = fmax(umax, (double)fabs(ur) + (double)fabs(ui));
       }
 #pragma unroll
       for (int s = 0; s < RT; ++s) {
@@ -349,9 +363,9 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         if (t < ntiles && 16 * t >= r0 + NB) {
           // A operand: L[16t + q][r0 + KPL g + ks] read from original row
           const int ra = S.perm[16 * t + q];
-          const double* pa_r = Fr + (size_t)ra * Np + r0 + KPL * g;
-          const double* pa_i = Fi + (size_t)ra * Np + r0 + KPL * g;
-          double ar[KPL], ai[KPL];
+          const T* pa_r = Fr + (size_t)ra * Np + r0 + KPL * g;
+          const T* pa_i = Fi + (size_t)ra * Np + r0 + KPL * g;
+          T ar[KPL], ai[KPL];
 #pragma unroll
           for (int k = 0; k < KPL; ++k) { ar[k] = pa_r[k]; ai[k] = pa_i[k]; }
 #pragma unroll
@@ -359,12 +373,12 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
             const int k = KPL * g + ks;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-              const double br = S.unr[k * LD(NB) + 16 * ct + q];
-              const double bi = S.uni[k * LD(NB) + 16 * ct + q];
-              xr[s][ct] = mfma(ar[ks], br, xr[s][ct]);
-              xr[s][ct] = mfma(-ai[ks], bi, xr[s][ct]);
-              xi[s][ct] = mfma(ar[ks], bi, xi[s][ct]);
-              xi[s][ct] = mfma(ai[ks], br, xi[s][ct]);
+              const T br = S.unr[k * LD(NB) + 16 * ct + q];
+              const T bi = S.uni[k * LD(NB) + 16 * ct + q];
+              xr[s][ct] = M::mma(ar[ks], br, xr[s][ct]);
+              xr[s][ct] = M::mma(-ai[ks], bi, xr[s][ct]);
+              xi[s][ct] = M::mma(ar[ks], bi, xi[s][ct]);
+              xi[s][ct] = M::mma(ai[ks], br, xi[s][ct]);
             }
           }
         }
@@ -387,10 +401,10 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         const int j = 16 * cj + qj;
         const int pj = c0 + j;
         const int par = j & 1;
-        double* slr = S.slr + par * WAVES * NB;
-        double* sli = S.sli + par * WAVES * NB;
-        double* rar = S.rAr + par * NB;
-        double* rai = S.rAi + par * NB;
+        T* slr = S.slr + par * WAVES * NB;
+        T* sli = S.sli + par * WAVES * NB;
+        T* rar = S.rAr + par * NB;
+        T* rai = S.rAi + par * NB;
         // A: wave candidate
         double best = -1.0;
         int brow = 0x7fffffff;
@@ -401,8 +415,8 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
             if (t < ntiles && 16 * t + 15 >= pj) {
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const int p = 16 * t + crow(g, i);
-                const double m = fabs(xr[s][cj][i]) + fabs(xi[s][cj][i]);
+                const int p = 16 * t + M::m(g, i);
+                const double m = (double)fabs(xr[s][cj][i]) + (double)fabs(xi[s][cj][i]);
                 if (p >= pj && m > best) { best = m; brow = p; }
               }
             }
@@ -423,7 +437,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           if (t < ntiles && 16 * t + 15 >= pj) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int p = 16 * t + crow(g, i);
+              const int p = 16 * t + M::m(g, i);
               if (p == wrow) {
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
@@ -451,19 +465,19 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           const int rr = S.crowi[par * WAVES + ww];
           if (m > bm || (m == bm && rr < piv)) { bm = m; piv = rr; wwin = ww; }
         }
-        const double* pvr_s = slr + wwin * NB;
-        const double* pvi_s = sli + wwin * NB;
+        const T* pvr_s = slr + wwin * NB;
+        const T* pvi_s = sli + wwin * NB;
         if (piv >= Np) {   // no comparable entry (NaN column): keep row pj
           piv = pj;
           pvr_s = rar;
           pvi_s = rai;
         }
-        double prr[CT], pri[CT];
+        T prr[CT], pri[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) { prr[ct] = pvr_s[16 * ct + q]; pri[ct] = pvi_s[16 * ct + q]; }
         const double pvr = pvr_s[j], pvi = pvi_s[j];
         const double rden = 1.0 / (pvr * pvr + pvi * pvi);
-        const double ivr = pvr * rden, ivi = -pvi * rden;
+        const T ivr = T(pvr * rden), ivi = T(-pvi * rden);
         // C: swap; multipliers below the pivot (owner lanes of column j)
 #pragma unroll
         for (int s = 0; s < RT; ++s) {
@@ -471,7 +485,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           if (t < ntiles && 16 * t + 15 >= pj) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int p = 16 * t + crow(g, i);
+              const int p = 16 * t + M::m(g, i);
               if (piv != pj && p == pj) {
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) { xr[s][ct][i] = prr[ct]; xi[s][ct][i] = pri[ct]; }
@@ -483,9 +497,9 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
                 }
               }
               if (q == qj && p > pj) {
-                const double ar = xr[s][cj][i], ai = xi[s][cj][i];
-                const double lr = ar * ivr - ai * ivi;
-                const double li = ar * ivi + ai * ivr;
+                const T ar = xr[s][cj][i], ai = xi[s][cj][i];
+                const T lr = ar * ivr - ai * ivi;
+                const T li = ar * ivi + ai * ivr;
                 xr[s][cj][i] = lr;
                 xi[s][cj][i] = li;
                 S.mr[p] = lr;
@@ -501,7 +515,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
             S.perm[piv] = tp;
           }
         }
-        if (tid >= j && tid < NB) umax = fmax(umax, fabs(pvr_s[tid]) + fabs(pvi_s[tid]));
+        if (tid >= j && tid < NB) umax = fmax(umax, (double)fabs(pvr_s[tid]) + (double)fabs(pvi_s[tid]));
         // the multipliers of this wave's rows were written by this wave
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -512,9 +526,9 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           if (t < ntiles && 16 * t + 15 > pj) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int p = 16 * t + crow(g, i);
+              const int p = 16 * t + M::m(g, i);
               if (p > pj) {
-                const double lr = S.mr[p], li = S.mi[p];
+                const T lr = S.mr[p], li = S.mi[p];
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
                   if (16 * ct + q > j) {
@@ -537,7 +551,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       if (t >= (c0 >> 4) && t < ((c0 + NB) >> 4)) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int pr = 16 * t + crow(g, i) - c0;
+          const int pr = 16 * t + M::m(g, i) - c0;
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             S.xsr[pr * LD(NB) + 16 * ct + q] = xr[s][ct][i];
@@ -553,7 +567,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       if (t < ntiles && 16 * t >= c0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int r = S.perm[16 * t + crow(g, i)];
+          const int r = S.perm[16 * t + M::m(g, i)];
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             Fr[(size_t)r * Np + c0 + 16 * ct + q] = xr[s][ct][i];
@@ -564,13 +578,13 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     }
     // ---- 6. inverses of the diagonal blocks L_JJ (unit) and U_JJ --------
     __syncthreads();
-    block_tri_inverses<NB, NT>(S.xsr, S.xsi, S.lsr, S.lsi, S.unr, S.uni,
+    block_tri_inverses<T, NB, NT>(S.xsr, S.xsi, S.lsr, S.lsi, S.unr, S.uni,
                                S.tr_, S.ti_, tid);
     {
-      double* Lr = T + (size_t)(J * 4 + 0) * NB * NB;
-      double* Li = Lr + NB * NB;
-      double* Ur = Li + NB * NB;
-      double* Ui = Ur + NB * NB;
+      T* Lr = Tb + (size_t)(J * 4 + 0) * NB * NB;
+      T* Li = Lr + NB * NB;
+      T* Ur = Li + NB * NB;
+      T* Ui = Ur + NB * NB;
       for (int e = tid; e < NB * NB; e += NT) {
         const int rr = e / NB, cc = e % NB;
         Lr[e] = S.lsr[rr * LD(NB) + cc];
@@ -588,7 +602,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   // strided partial sums, then a fixed-order combination
   for (int p = tid; p < Np; p += NT) {
     const size_t e = (size_t)S.perm[p] * Np + p;
-    lsum += log(hypot(Fr[e], Fi[e]));
+    lsum += log(hypot((double)Fr[e], (double)Fi[e]));
   }
   // growth = max|u| / max|a| over the block
   for (int off = 32; off >= 1; off >>= 1) {
@@ -596,13 +610,13 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     amax = fmax(amax, __shfl_xor(amax, off));
   }
   __syncthreads();
-  if (lane == 0) { S.mr[w] = umax; S.mi[w] = amax; }
-  S.slr[tid] = lsum;   // slot area: 4 WAVES NB >= NT doubles
+  if (lane == 0) { S.cmag[w] = umax; S.cmag[WAVES + w] = amax; }
+  S.red[tid] = lsum;
   __syncthreads();
   if (tid == 0) {
     double u = 0.0, a = 0.0, l = 0.0;
-    for (int ww = 0; ww < WAVES; ++ww) { u = fmax(u, S.mr[ww]); a = fmax(a, S.mi[ww]); }
-    for (int k = 0; k < NT; ++k) l += S.slr[k];
+    for (int ww = 0; ww < WAVES; ++ww) { u = fmax(u, S.cmag[ww]); a = fmax(a, S.cmag[WAVES + ww]); }
+    for (int k = 0; k < NT; ++k) l += S.red[k];
     growth[b] = u / a;
     lad[b] = l;
   }
@@ -615,14 +629,17 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
 // Each step forms Y = U[I,J] U_JJ^-1 (or L[K,J] L_JJ^-1) in LDS, then the
 // waves accumulate their row tiles with the f64 MFMA.  W[a][k] lives where
 // U[a][k] was (row perm[a]), V[r][k] where L[r][k] was.
+template <typename T>
 size_t trtri_lds_bytes(int Np, int NB) {
-  return sizeof(int) * Np + sizeof(double) * 6 * NB * (NB + 1) + 64;
+  return sizeof(int) * Np + sizeof(T) * 6 * NB * (NB + 1) + 64;
 }
 
-template <int WAVES, int RT, int CT>
+template <typename T, int WAVES, int RT, int CT>
 __global__ void __launch_bounds__(WAVES * 64)
-trtri_kernel(int Np, double* __restrict__ F, const int* __restrict__ perm_g,
-             const double* __restrict__ tri) {
+trtri_kernel(int Np, T* __restrict__ F, const int* __restrict__ perm_g,
+             const T* __restrict__ tri) {
+  typedef Mma<T> M;
+  typedef typename M::v4 V4;
   constexpr int NB = 16 * CT;
   constexpr int NT = WAVES * 64;
   constexpr int KPL = NB / 4;
@@ -633,17 +650,17 @@ trtri_kernel(int Np, double* __restrict__ F, const int* __restrict__ perm_g,
   const int g = lane >> 4, q = lane & 15;
   const int ntiles = Np >> 4;
   const int nblk = Np / NB;
-  double* xsr = lds_raw;                 // block of U or L
-  double* xsi = xsr + NB * LD(NB);
-  double* dir = xsi + NB * LD(NB);       // U_JJ^-1 or L_JJ^-1
-  double* dii = dir + NB * LD(NB);
-  double* yr_s = dii + NB * LD(NB);      // Y
-  double* yi_s = yr_s + NB * LD(NB);
+  T* xsr = reinterpret_cast<T*>(lds_raw);   // block of U or L
+  T* xsi = xsr + NB * LD(NB);
+  T* dir = xsi + NB * LD(NB);       // U_JJ^-1 or L_JJ^-1
+  T* dii = dir + NB * LD(NB);
+  T* yr_s = dii + NB * LD(NB);      // Y
+  T* yi_s = yr_s + NB * LD(NB);
   int* perm = reinterpret_cast<int*>(yi_s + NB * LD(NB));
   const size_t plane = (size_t)Np * Np;
-  double* Fr = F + (size_t)b * 2 * plane;
-  double* Fi = Fr + plane;
-  const double* T = tri + (size_t)b * nblk * 4 * NB * NB;
+  T* Fr = F + (size_t)b * 2 * plane;
+  T* Fi = Fr + plane;
+  const T* Tb = tri + (size_t)b * nblk * 4 * NB * NB;
   for (int p = tid; p < Np; p += NT) perm[p] = perm_g[(size_t)b * Np + p];
 
   for (int jj = 0; jj < nblk; ++jj) {
@@ -651,20 +668,20 @@ trtri_kernel(int Np, double* __restrict__ F, const int* __restrict__ perm_g,
     const int c0 = J * NB;
     __syncthreads();
     {
-      const double* Dr = T + (size_t)(J * 4 + (upper ? 2 : 0)) * NB * NB;
-      const double* Di = Dr + NB * NB;
+      const T* Dr = Tb + (size_t)(J * 4 + (upper ? 2 : 0)) * NB * NB;
+      const T* Di = Dr + NB * NB;
       for (int e = tid; e < NB * NB; e += NT) {
         dir[(e / NB) * LD(NB) + e % NB] = Dr[e];
         dii[(e / NB) * LD(NB) + e % NB] = Di[e];
       }
     }
-    d4 ar_[RT][CT], ai_[RT][CT];
+    V4 ar_[RT][CT], ai_[RT][CT];
 #pragma unroll
     for (int s = 0; s < RT; ++s)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
-        ar_[s][ct] = (d4){0.0, 0.0, 0.0, 0.0};
-        ai_[s][ct] = (d4){0.0, 0.0, 0.0, 0.0};
+        ar_[s][ct] = (V4){T(0), T(0), T(0), T(0)};
+        ai_[s][ct] = (V4){T(0), T(0), T(0), T(0)};
       }
     const int nsteps = upper ? J : nblk - 1 - J;
     for (int st = 0; st < nsteps; ++st) {
@@ -681,21 +698,21 @@ trtri_kernel(int Np, double* __restrict__ F, const int* __restrict__ perm_g,
       // Y = X_blk * D  (D = U_JJ^-1 or L_JJ^-1)
       for (int task = w; task < 2 * CT * CT; task += WAVES) {
         const int rt = task / (2 * CT), ct = (task >> 1) % CT, part = task & 1;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        V4 acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int ks = 0; ks < NB / 4; ++ks) {
           const int k = 4 * ks + g;
-          const double a_r = xsr[(16 * rt + q) * LD(NB) + k];
-          const double a_i = xsi[(16 * rt + q) * LD(NB) + k];
-          const double b_r = dir[k * LD(NB) + 16 * ct + q];
-          const double b_i = dii[k * LD(NB) + 16 * ct + q];
-          if (part == 0) { acc = mfma(a_r, b_r, acc); acc = mfma(-a_i, b_i, acc); }
-          else { acc = mfma(a_r, b_i, acc); acc = mfma(a_i, b_r, acc); }
+          const T a_r = xsr[(16 * rt + q) * LD(NB) + k];
+          const T a_i = xsi[(16 * rt + q) * LD(NB) + k];
+          const T b_r = dir[k * LD(NB) + 16 * ct + q];
+          const T b_i = dii[k * LD(NB) + 16 * ct + q];
+          if (part == 0) { acc = M::mma(a_r, b_r, acc); acc = M::mma(-a_i, b_i, acc); }
+          else { acc = M::mma(a_r, b_i, acc); acc = M::mma(a_i, b_r, acc); }
         }
-        double* dst = part ? yi_s : yr_s;
+        T* dst = part ? yi_s : yr_s;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          dst[(16 * rt + crow(g, i)) * LD(NB) + 16 * ct + q] = acc[i];
+          dst[(16 * rt + M::m(g, i)) * LD(NB) + 16 * ct + q] = acc[i];
       }
       __syncthreads();
       // acc[rows] += Tri[rows, I-cols] * Y, rows in the triangle's reach
@@ -707,18 +724,18 @@ trtri_kernel(int Np, double* __restrict__ F, const int* __restrict__ perm_g,
         if (active) {
           const int arow = 16 * t + q;     // A-operand row (position)
           const int orow = perm[arow];
-          const double* pa_r = Fr + (size_t)orow * Np + r0 + KPL * g;
-          const double* pa_i = Fi + (size_t)orow * Np + r0 + KPL * g;
-          double a_r[KPL], a_i[KPL];
+          const T* pa_r = Fr + (size_t)orow * Np + r0 + KPL * g;
+          const T* pa_i = Fi + (size_t)orow * Np + r0 + KPL * g;
+          T a_r[KPL], a_i[KPL];
 #pragma unroll
           for (int k = 0; k < KPL; ++k) {
             const int col = r0 + KPL * g + k;
-            double vr = pa_r[k], vi = pa_i[k];
+            T vr = pa_r[k], vi = pa_i[k];
             if (upper) {
-              if (col < arow) { vr = 0.0; vi = 0.0; }
+              if (col < arow) { vr = T(0); vi = T(0); }
             } else {
-              if (col > arow) { vr = 0.0; vi = 0.0; }
-              else if (col == arow) { vr = 1.0; vi = 0.0; }
+              if (col > arow) { vr = T(0); vi = T(0); }
+              else if (col == arow) { vr = T(1); vi = T(0); }
             }
             a_r[k] = vr; a_i[k] = vi;
           }
@@ -727,12 +744,12 @@ trtri_kernel(int Np, double* __restrict__ F, const int* __restrict__ perm_g,
             const int k = KPL * g + ks;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-              const double b_r = yr_s[k * LD(NB) + 16 * ct + q];
-              const double b_i = yi_s[k * LD(NB) + 16 * ct + q];
-              ar_[s][ct] = mfma(a_r[ks], b_r, ar_[s][ct]);
-              ar_[s][ct] = mfma(-a_i[ks], b_i, ar_[s][ct]);
-              ai_[s][ct] = mfma(a_r[ks], b_i, ai_[s][ct]);
-              ai_[s][ct] = mfma(a_i[ks], b_r, ai_[s][ct]);
+              const T b_r = yr_s[k * LD(NB) + 16 * ct + q];
+              const T b_i = yi_s[k * LD(NB) + 16 * ct + q];
+              ar_[s][ct] = M::mma(a_r[ks], b_r, ar_[s][ct]);
+              ar_[s][ct] = M::mma(-a_i[ks], b_i, ar_[s][ct]);
+              ai_[s][ct] = M::mma(a_r[ks], b_i, ai_[s][ct]);
+              ai_[s][ct] = M::mma(a_i[ks], b_r, ai_[s][ct]);
             }
           }
         }
@@ -748,7 +765,7 @@ trtri_kernel(int Np, double* __restrict__ F, const int* __restrict__ perm_g,
       if (active) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int orow = perm[16 * t + crow(g, i)];
+          const int orow = perm[16 * t + M::m(g, i)];
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             Fr[(size_t)orow * Np + c0 + 16 * ct + q] = -ar_[s][ct][i];
@@ -776,8 +793,9 @@ trtri_kernel(int Np, double* __restrict__ F, const int* __restrict__ perm_g,
 constexpr int kDD = 32;
 constexpr int kDDParts = 8;   // 256 threads = 32 positions x 8 s-slices
 
+template <typename T>
 __global__ void __launch_bounds__(256)
-diagdot_kernel(int N, int Np, const double* __restrict__ F,
+diagdot_kernel(int N, int Np, const T* __restrict__ F,
                const int* __restrict__ perm_g, double* __restrict__ dg) {
   const int j0 = blockIdx.x * kDD;
   const int b = blockIdx.y;
@@ -787,8 +805,8 @@ diagdot_kernel(int N, int Np, const double* __restrict__ F,
   __shared__ int wrow[kDD], lo[kDD];
   __shared__ double pr_s[kDDParts][kDD], pi_s[kDDParts][kDD];
   const size_t plane = (size_t)Np * Np;
-  const double* Fr = F + (size_t)b * 2 * plane;
-  const double* Fi = Fr + plane;
+  const T* Fr = F + (size_t)b * 2 * plane;
+  const T* Fi = Fr + plane;
   const int* perm = perm_g + (size_t)b * Np;
   if (tid < kDD) {
     const int j = j0 + tid;
@@ -860,58 +878,80 @@ diagdot_kernel(int N, int Np, const double* __restrict__ F,
 
 namespace {
 
-template <int WAVES, int RT, int CT>
+template <typename T, int WAVES, int RT, int CT>
 hipError_t run_lu(const MatDesc* descs, const double* hbuf, int B, int N,
-                  int Np, int L, double* F, int* perm, double* tri,
-                  double* lad, double* growth, hipStream_t st) {
-  const size_t lds = lu_lds_bytes(Np, 16 * CT, WAVES);
+                  int Np, int L, T* F, int* perm, T* tri, double* lad,
+                  double* growth, hipStream_t st) {
+  const size_t lds = lu_lds_bytes<T>(Np, 16 * CT, WAVES);
+  auto kern = lu_kernel<T, WAVES, RT, CT>;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
   mark_begin(K_LU, st);
-  hipLaunchKernelGGL((lu_kernel<WAVES, RT, CT>), dim3(B), dim3(WAVES * 64),
-                     lds, st, descs, hbuf, N, Np, L, F, perm, tri, lad, growth);
+  hipLaunchKernelGGL(kern, dim3(B), dim3(WAVES * 64), lds, st, descs, hbuf, N,
+                     Np, L, F, perm, tri, lad, growth);
   mark_end(K_LU, st);
   return hipGetLastError();
 }
 
-template <int WAVES, int RT, int CT>
-hipError_t run_inv(int B, int N, int Np, double* F, const int* perm,
-                   const double* tri, double* dg, hipStream_t st) {
-  const size_t lds = trtri_lds_bytes(Np, 16 * CT);
+template <typename T, int WAVES, int RT, int CT>
+hipError_t run_trtri(int B, int Np, T* F, const int* perm, const T* tri,
+                     hipStream_t st) {
+  const size_t lds = trtri_lds_bytes<T>(Np, 16 * CT);
   mark_begin(K_TRTRI, st);
-  hipLaunchKernelGGL((trtri_kernel<WAVES, RT, CT>), dim3(B, 2), dim3(WAVES * 64),
-                     lds, st, Np, F, perm, tri);
+  hipLaunchKernelGGL((trtri_kernel<T, WAVES, RT, CT>), dim3(B, 2),
+                     dim3(WAVES * 64), lds, st, Np, F, perm, tri);
   mark_end(K_TRTRI, st);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_diagdot(int B, int N, int Np, const T* F, const int* perm,
+                       double* dg, hipStream_t st) {
   mark_begin(K_DIAGDOT, st);
-  hipLaunchKernelGGL(diagdot_kernel, dim3((Np + kDD - 1) / kDD, B), dim3(256),
-                     0, st, N, Np, F, perm, dg);
+  hipLaunchKernelGGL(diagdot_kernel<T>, dim3((Np + kDD - 1) / kDD, B),
+                     dim3(256), 0, st, N, Np, F, perm, dg);
   mark_end(K_DIAGDOT, st);
   return hipGetLastError();
 }
 
 }  // namespace
 
-BlockedPlan blocked_plan_f64(int N) {
-  // cfg 0: 4 waves x 4 row tiles (Np <= 256), cfg 1: 8 x 4 (Np <= 512), both
-  // with 32-wide blocks; cfg 2: 16-wide blocks for Np <= 1024 (LU on 16
-  // waves x 4 tiles, inverses on 8 x 8).
+BlockedPlan blocked_plan(int N, bool fp32) {
+  // Row tiles of 16 per wave; the block column (Np rows x NB) lives in MFMA
+  // accumulators.  FP64: 4 waves x 4 tiles (Np <= 256), 8 x 4 (Np <= 512)
+  // with NB = 32, then NB = 16 up to Np = 1024.  FP32 (half the registers):
+  // the same up to 512, NB = 32 on 8 x 8 tiles up to 1024, NB = 16 on
+  // 8 x 18 tiles up to 2304; Np is a multiple of 64 there, the tile of the
+  // W V product that follows.
   BlockedPlan p{};
-  const int n32 = (N + 31) / 32 * 32;
-  if (n32 <= 256) { p.cfg = 0; p.NB = 32; p.Np = n32; }
-  else if (n32 <= 512) { p.cfg = 1; p.NB = 32; p.Np = n32; }
-  else if (N <= 1024) { p.cfg = 2; p.NB = 16; p.Np = (N + 15) / 16 * 16; }
-  else { p.cfg = -1; p.NB = 0; p.Np = 0; }
+  p.cfg = -1;
+  if (!fp32) {
+    const int n32 = (N + 31) / 32 * 32, n16 = (N + 15) / 16 * 16;
+    if (n32 <= 256) { p.cfg = 0; p.NB = 32; p.Np = n32; }
+    else if (n32 <= 512) { p.cfg = 1; p.NB = 32; p.Np = n32; }
+    else if (n16 <= 1024) { p.cfg = 2; p.NB = 16; p.Np = n16; }
+  } else {
+    const int n64 = (N + 63) / 64 * 64;
+    if (n64 <= 256) { p.cfg = 0; p.NB = 32; p.Np = n64; }
+    else if (n64 <= 512) { p.cfg = 1; p.NB = 32; p.Np = n64; }
+    else if (n64 <= 1024) { p.cfg = 2; p.NB = 32; p.Np = n64; }
+    else if (n64 <= 2304) { p.cfg = 3; p.NB = 16; p.Np = n64; }
+  }
+  if (p.cfg < 0) { p.NB = 0; p.Np = 0; }
   return p;
 }
+
+BlockedPlan blocked_plan_f64(int N) { return blocked_plan(N, false); }
 
 hipError_t blocked_lu_f64(const BlockedPlan& p, const MatDesc* descs,
                           const double* hbuf, int B, int N, int L, double* F,
                           int* perm, double* tri, double* lad, double* growth,
                           hipStream_t st) {
   switch (p.cfg) {
-    case 0: return run_lu<4, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
-    case 1: return run_lu<8, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
-    case 2: return run_lu<16, 4, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 0: return run_lu<double, 4, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 1: return run_lu<double, 8, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 2: return run_lu<double, 16, 4, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -919,20 +959,52 @@ hipError_t blocked_lu_f64(const BlockedPlan& p, const MatDesc* descs,
 hipError_t blocked_inv_f64(const BlockedPlan& p, int B, int N, double* F,
                            const int* perm, const double* tri, double* dg,
                            hipStream_t st) {
+  hipError_t e;
   switch (p.cfg) {
-    case 0: return run_inv<4, 4, 2>(B, N, p.Np, F, perm, tri, dg, st);
-    case 1: return run_inv<8, 4, 2>(B, N, p.Np, F, perm, tri, dg, st);
-    case 2: return run_inv<8, 8, 1>(B, N, p.Np, F, perm, tri, dg, st);
+    case 0: e = run_trtri<double, 4, 4, 2>(B, p.Np, F, perm, tri, st); break;
+    case 1: e = run_trtri<double, 8, 4, 2>(B, p.Np, F, perm, tri, st); break;
+    case 2: e = run_trtri<double, 8, 8, 1>(B, p.Np, F, perm, tri, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  return run_diagdot<double>(B, N, p.Np, F, perm, dg, st);
+}
+
+hipError_t blocked_lu_f32(const BlockedPlan& p, const MatDesc* descs,
+                          const double* hbuf, int B, int N, int L, float* F,
+                          int* perm, float* tri, double* lad, double* growth,
+                          hipStream_t st) {
+  switch (p.cfg) {
+    case 0: return run_lu<float, 4, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 1: return run_lu<float, 8, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 2: return run_lu<float, 8, 8, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 3: return run_lu<float, 8, 18, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-size_t blocked_factor_bytes_f64(const BlockedPlan& p, int B) {
+hipError_t blocked_trtri_f32(const BlockedPlan& p, int B, float* F,
+                             const int* perm, const float* tri,
+                             hipStream_t st) {
+  switch (p.cfg) {
+    case 0: return run_trtri<float, 4, 4, 2>(B, p.Np, F, perm, tri, st);
+    case 1: return run_trtri<float, 8, 4, 2>(B, p.Np, F, perm, tri, st);
+    case 2: return run_trtri<float, 8, 8, 2>(B, p.Np, F, perm, tri, st);
+    case 3: return run_trtri<float, 8, 18, 1>(B, p.Np, F, perm, tri, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t blocked_factor_bytes(const BlockedPlan& p, int B, size_t elem) {
   const size_t Np = p.Np, NB = p.NB;
-  const size_t F = 2 * Np * Np * sizeof(double);
+  const size_t F = 2 * Np * Np * elem;
   const size_t perm = Np * sizeof(int);
-  const size_t tri = (Np / NB) * 4 * NB * NB * sizeof(double);
+  const size_t tri = (Np / NB) * 4 * NB * NB * elem;
   return (size_t)B * (F + perm + tri) + 3 * 256;
+}
+
+size_t blocked_factor_bytes_f64(const BlockedPlan& p, int B) {
+  return blocked_factor_bytes(p, B, sizeof(double));
 }
 
 }  // namespace sca

@@ -264,6 +264,15 @@ sca_status begin_call(sca_ctx* ctx, const sca_params* p) {
   return check_dev_ptr(ctx, p->onsite, "params.onsite", true);
 }
 
+// Pivot growth above which a complex64 factorisation is not trusted: the
+// backward error of an LU grows with it, and the FP64 refinement only
+// corrects an error of FP32 size.
+constexpr double kFp32GrowthMax = 1e3;
+
+bool growth_exceeded(int precision, double growth) {
+  return precision == SCA_FP32_REFINED && !(growth <= kFp32GrowthMax);
+}
+
 sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
                        double* grad, double* omega2, ProbStats* st_out) {
   const int N = p->L * p->L, M = p->n_max, B = 2 * M;
@@ -279,6 +288,14 @@ sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
   ProbStats S;
   s = read_stats(ctx, c, 1, &S);
   if (s) return s;
+  if (growth_exceeded(p->precision, S.pivot_growth) && !S.nonfinite) {
+    if (!path_supported(N, SCA_FP64))
+      return fail(SCA_ENUMERIC, "FP32 pivot growth %.3g above %.0e and no "
+                  "FP64 path for N=%d", S.pivot_growth, kFp32GrowthMax, N);
+    sca_params q = *p;
+    q.precision = SCA_FP64;
+    return eval_single(ctx, &q, phi, grad, omega2, st_out);
+  }
   if (omega2) {
     double o2[2] = {S.omega, S.omega_tilde};
     HIP_TRY(hipMemcpyAsync(omega2, o2, sizeof o2, hipMemcpyHostToDevice,
@@ -381,20 +398,27 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
   if ((s = check_dev_ptr(ctx, v, "v"))) return s;
 
   const int N = p->L * p->L, M = p->n_max, B = 2 * M;
-  const size_t fb = factor_workspace_bytes(N, B, p->precision);
-  Carve c0 = carve(nullptr, 1, N, B, p->precision, true, true, fb);
-  if ((s = ensure_ws(ctx, c0.total))) return s;
-  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, true, true, fb);
+  int prec = p->precision;
+  Carve c;
+  auto setup = [&]() -> sca_status {
+    const size_t fb = factor_workspace_bytes(N, B, prec);
+    Carve c0 = carve(nullptr, 1, N, B, prec, true, true, fb);
+    sca_status r = ensure_ws(ctx, c0.total);
+    if (r) return r;
+    c = carve((char*)ctx->ws, 1, N, B, prec, true, true, fb);
+    return SCA_OK;
+  };
+  if ((s = setup())) return s;
   ProbDesc P = make_prob(p, phi, nullptr);
   P.m = m; P.v = v; P.phi_out = phi;
   AdamHyper hy{o->lr, o->beta1, o->beta2, o->eps};
   std::memset(res, 0, sizeof *res);
   int done = 0;
-  bool converged = false;
+  bool converged = false, upload = true;
   for (int k = 1; k <= o->n_steps; ++k) {
-    s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, o->t0 + k, hy,
-                  k == 1);
+    s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, o->t0 + k, hy, upload);
     if (s) return s;
+    upload = false;
     done = k;
     if (o->check_every > 0 && k % o->check_every == 0) {
       ProbStats S;
@@ -403,6 +427,15 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
         res->steps_done = done;
         res->flags |= SCA_FLAG_NONFINITE;
         return fail(SCA_ENUMERIC, "non-finite value at step %d", o->t0 + k);
+      }
+      if (growth_exceeded(prec, S.pivot_growth)) {
+        // the remaining steps run in FP64 where that path is built
+        res->flags |= SCA_FLAG_PIVOT_GROWTH;
+        if (path_supported(N, SCA_FP64)) {
+          prec = SCA_FP64;
+          if ((s = setup())) return s;
+          upload = true;
+        }
       }
       if (o->grad_tol > 0.0 && S.max_abs_grad < o->grad_tol) {
         converged = true;
@@ -416,10 +449,12 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
     if ((s = read_stats(ctx, c, 1, &S))) return s;
   } else {
     // statistics at the returned phi
-    s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, 0, hy, done == 0);
+    s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, 0, hy, upload);
     if (s) return s;
     if ((s = read_stats(ctx, c, 1, &S))) return s;
   }
+  if (growth_exceeded(prec, S.pivot_growth))
+    res->flags |= SCA_FLAG_PIVOT_GROWTH;
   res->omega = S.omega;
   res->omega_tilde = S.omega_tilde;
   res->af_order = S.af_order;

@@ -6,11 +6,13 @@
 
 namespace sca {
 
-// Launch configuration of the blocked FP64 path for N sites: cfg selects
-// the (waves, row tiles per wave, block width) instance, Np is N rounded up
-// to the block width NB.  cfg < 0: N too large for FP64.
+// Launch configuration of a blocked path for N sites: cfg selects the
+// (waves, row tiles per wave, block width) instance, Np is N rounded up to
+// the block width NB.  cfg < 0: N too large for that precision.
 struct BlockedPlan { int cfg, NB, Np; };
+BlockedPlan blocked_plan(int N, bool fp32);
 BlockedPlan blocked_plan_f64(int N);
+size_t blocked_factor_bytes(const BlockedPlan& p, int B, size_t elem);
 
 // Bytes of the factor storage of B matrices: F [B][2][Np][Np] doubles,
 // perm [B][Np] int32, diagonal-block inverses [B][Np/NB][2][2][NB][NB].
@@ -28,5 +30,24 @@ hipError_t blocked_lu_f64(const BlockedPlan& p, const MatDesc* descs,
 hipError_t blocked_inv_f64(const BlockedPlan& p, int B, int N, double* F,
                            const int* perm, const double* tri, double* dg,
                            hipStream_t st);
+
+// FP32 factor route (k_factor.hip, k_refine.hip).
+hipError_t blocked_lu_f32(const BlockedPlan& p, const MatDesc* descs,
+                          const double* hbuf, int B, int N, int L, float* F,
+                          int* perm, float* tri, double* lad, double* growth,
+                          hipStream_t st);
+hipError_t blocked_trtri_f32(const BlockedPlan& p, int B, float* F,
+                             const int* perm, const float* tri,
+                             hipStream_t st);
+// X = fl32(W V) for every matrix (Np a multiple of 64).
+hipError_t launch_wv_gemm(int B, int Np, const float* F, const int* perm,
+                          float* X, hipStream_t st);
+// FP64 Newton diagonal -> dg[b][N][2] and refined ln|det| -> lad[b];
+// ldpart: B * refine_blocks(Np) doubles of scratch.
+int refine_blocks(int Np);
+hipError_t launch_refine(int B, int N, int Np, int L, const MatDesc* descs,
+                         const double* hbuf, const float* F, const int* perm,
+                         const float* X, double* dg, double* ldpart,
+                         double* lad, hipStream_t st);
 
 }  // namespace sca

@@ -1,7 +1,10 @@
 // Factorisation path selection.
 //   N <= 64  : fused small kernel (matrix in LDS), FP64 for both precisions
 //              (these matrices are too small for the FP32 route to pay).
-//   N <= 1024: blocked FP64 path (LU, then U^-1 / L^-1, then the diagonal).
+//   FP64, N <= 1024: blocked LU, then U^-1 / L^-1, then the diagonal.
+//   FP32 refined, N <= 2304: blocked complex64 LU and U^-1 / L^-1, the
+//              product X = W V, then the FP64 Newton diagonal and the
+//              refined log-determinant.
 #include "sca_blocked.h"
 #include "sca_common.h"
 #include "sca_kernels.h"
@@ -17,29 +20,63 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 bool path_supported(int N, int precision) {
   if (N < 1) return false;
   if (N <= kSmallMax) return true;
-  if (precision == 0) return blocked_plan_f64(N).cfg >= 0;
-  return false;
-}
-
-size_t factor_workspace_bytes(int N, int B, int precision) {
-  (void)precision;
-  if (N <= kSmallMax) return 0;
-  return blocked_factor_bytes_f64(blocked_plan_f64(N), B);
+  return blocked_plan(N, precision != 0).cfg >= 0;
 }
 
 namespace {
 
-struct BlockedBufs { double* F; int* perm; double* tri; };
+size_t refine_extra_bytes(const BlockedPlan& p, int B) {
+  return align256(sizeof(float) * 2 * (size_t)B * p.Np * p.Np)        // X
+       + align256(sizeof(double) * (size_t)B * refine_blocks(p.Np));  // parts
+}
 
-BlockedBufs carve_blocked(void* fact, const BlockedPlan& p, int B) {
+}  // namespace
+
+size_t factor_workspace_bytes(int N, int B, int precision) {
+  if (N <= kSmallMax) return 0;
+  const BlockedPlan p = blocked_plan(N, precision != 0);
+  if (p.cfg < 0) return 0;
+  if (precision == 0) return blocked_factor_bytes(p, B, sizeof(double));
+  return blocked_factor_bytes(p, B, sizeof(float)) + refine_extra_bytes(p, B);
+}
+
+namespace {
+
+// F (planar re/im factors, B x 2 x Np x Np), perm (B x Np), tri (inverted
+// diagonal blocks); the FP32 route adds X (B x 2 x Np x Np) and the
+// per-block log-det parts.
+template <typename T>
+struct BlockedBufs { T* F; int* perm; T* tri; float* X; double* parts; };
+
+template <typename T>
+BlockedBufs<T> carve_blocked(void* fact, const BlockedPlan& p, int B) {
   char* c = static_cast<char*>(fact);
-  BlockedBufs r;
-  r.F = reinterpret_cast<double*>(c);
-  c += align256(sizeof(double) * 2 * (size_t)B * p.Np * p.Np);
+  BlockedBufs<T> r{};
+  r.F = reinterpret_cast<T*>(c);
+  c += align256(sizeof(T) * 2 * (size_t)B * p.Np * p.Np);
   r.perm = reinterpret_cast<int*>(c);
   c += align256(sizeof(int) * (size_t)B * p.Np);
-  r.tri = reinterpret_cast<double*>(c);
+  r.tri = reinterpret_cast<T*>(c);
+  c += align256(sizeof(T) * (size_t)B * (p.Np / p.NB) * 4 * p.NB * p.NB);
+  r.X = reinterpret_cast<float*>(c);
+  c += align256(sizeof(float) * 2 * (size_t)B * p.Np * p.Np);
+  r.parts = reinterpret_cast<double*>(c);
   return r;
+}
+
+hipError_t fp32r_batch(const BlockedPlan& p, const MatDesc* descs,
+                       const double* hbuf, int B, int N, int L, double* lad,
+                       double* dg, double* growth, void* fact,
+                       hipStream_t st) {
+  BlockedBufs<float> bb = carve_blocked<float>(fact, p, B);
+  hipError_t e = blocked_lu_f32(p, descs, hbuf, B, N, L, bb.F, bb.perm,
+                                bb.tri, lad, growth, st);
+  if (e == hipSuccess) e = blocked_trtri_f32(p, B, bb.F, bb.perm, bb.tri, st);
+  if (e == hipSuccess) e = launch_wv_gemm(B, p.Np, bb.F, bb.perm, bb.X, st);
+  if (e == hipSuccess)
+    e = launch_refine(B, N, p.Np, L, descs, hbuf, bb.F, bb.perm, bb.X, dg,
+                      bb.parts, lad, st);
+  return e;
 }
 
 }  // namespace
@@ -47,13 +84,14 @@ BlockedBufs carve_blocked(void* fact, const BlockedPlan& p, int B) {
 hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
                         int L, int precision, double* lad, double* dg,
                         double* growth, void* fact, hipStream_t st) {
-  (void)precision;
   if (B <= 0) return hipSuccess;
   if (N <= kSmallMax)
     return launch_small_factor(descs, hbuf, B, N, L, lad, dg, growth, st);
-  const BlockedPlan p = blocked_plan_f64(N);
+  const BlockedPlan p = blocked_plan(N, precision != 0);
   if (p.cfg < 0) return hipErrorInvalidValue;
-  BlockedBufs bb = carve_blocked(fact, p, B);
+  if (precision != 0)
+    return fp32r_batch(p, descs, hbuf, B, N, L, lad, dg, growth, fact, st);
+  BlockedBufs<double> bb = carve_blocked<double>(fact, p, B);
   hipError_t e = blocked_lu_f64(p, descs, hbuf, B, N, L, bb.F, bb.perm, bb.tri,
                                 lad, growth, st);
   if (e != hipSuccess) return e;
@@ -85,24 +123,26 @@ AutogradLayout autograd_layout(void* base, int N, int B, int precision) {
 hipError_t factor_forward(const MatDesc* descs, const double* hbuf, int B,
                           int N, int L, int precision, double* lad, double* dg,
                           double* growth, void* fact, hipStream_t st) {
-  // the small path forms diag(A^-1) in the same pass as the LU
-  if (N <= kSmallMax)
+  // the small path forms diag(A^-1) in the same pass as the LU; the FP32
+  // route needs W and V for the refined log-determinant, so it completes
+  // the diagonal in the forward as well
+  if (N <= kSmallMax || precision != 0)
     return factor_batch(descs, hbuf, B, N, L, precision, lad, dg, growth, fact,
                         st);
   const BlockedPlan p = blocked_plan_f64(N);
   if (p.cfg < 0) return hipErrorInvalidValue;
-  BlockedBufs bb = carve_blocked(fact, p, B);
+  BlockedBufs<double> bb = carve_blocked<double>(fact, p, B);
   return blocked_lu_f64(p, descs, hbuf, B, N, L, bb.F, bb.perm, bb.tri, lad,
                         growth, st);
 }
 
 hipError_t factor_backward(int B, int N, int precision, const double* lad,
                            double* dg, void* fact, hipStream_t st) {
-  (void)lad; (void)precision;
-  if (N <= kSmallMax) return hipSuccess;   // dg already complete
+  (void)lad;
+  if (N <= kSmallMax || precision != 0) return hipSuccess;   // dg complete
   const BlockedPlan p = blocked_plan_f64(N);
   if (p.cfg < 0) return hipErrorInvalidValue;
-  BlockedBufs bb = carve_blocked(fact, p, B);
+  BlockedBufs<double> bb = carve_blocked<double>(fact, p, B);
   return blocked_inv_f64(p, B, N, bb.F, bb.perm, bb.tri, dg, st);
 }
 
