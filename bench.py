@@ -41,6 +41,10 @@ def kernel_work(kind: str, N: int, B: int):
         return B * 8.0 / 3.0 * n3, "flop", "mfma"
     if kind == "small":       # fused LU + both triangular inverses
         return B * 16.0 / 3.0 * n3, "flop", "mfma"
+    if kind == "wvgemm":      # X = W V, upper x unit lower: (8/3) N^3
+        return B * 8.0 / 3.0 * n3, "flop", "mfma"
+    if kind == "refine":      # reads X and the W, V triangles once (FP32)
+        return B * 16.0 * N * N, "byte", "hbm"
     if kind == "diagdot":     # reads the W and V triangles once
         return B * 16.0 * N * N, "byte", "hbm"
     if kind == "reduce":      # reads diag(A^-1) of every matrix

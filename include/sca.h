@@ -175,6 +175,7 @@ SCA_API sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
 #define SCA_K_REDUCE 4  /* Matsubara/spin reduction and ADAM update */
 #define SCA_K_SETUP 5   /* descriptors and diagonal vectors */
 #define SCA_K_REFINE 6  /* FP64 refinement of the FP32 route */
+#define SCA_K_WVGEMM 7  /* X = U^-1 L^-1 product of the FP32 route */
 SCA_API sca_status sca_profile(sca_ctx* ctx, int enable);
 SCA_API sca_status sca_profile_read(sca_ctx* ctx, double* total_ms,
                                     int64_t* launches);

@@ -20,7 +20,7 @@ SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH, SCA_FLAG_CONVERGED = 1, 2, 4
 SCA_ADAM_NO_FINAL_EVAL = 1
 PROFILE_SLOTS = 8
 KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
-                  "refine", "spare")
+                  "refine", "wvgemm")
 
 # Every symbol include/sca.h declares.
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",

@@ -340,10 +340,10 @@ int refine_blocks(int Np) { return (Np + RQ - 1) / RQ; }
 hipError_t launch_wv_gemm(int B, int Np, const float* F, const int* perm,
                           float* X, hipStream_t st) {
   if (Np % GT) return hipErrorInvalidValue;
-  mark_begin(K_TRTRI, st);
+  mark_begin(K_WVGEMM, st);
   hipLaunchKernelGGL(wv_gemm_kernel, dim3(Np / GT, Np / GT, B), dim3(256), 0,
                      st, Np, F, perm, X);
-  mark_end(K_TRTRI, st);
+  mark_end(K_WVGEMM, st);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ enum KernelClass {
   K_REDUCE = 4,   // Matsubara/spin reduction + ADAM
   K_SETUP = 5,    // descriptors and diagonal vectors
   K_REFINE = 6,   // FP64 refinement of the FP32 route
+  K_WVGEMM = 7,   // X = U^-1 L^-1 of the FP32 route
   K_COUNT = 8
 };
 
