@@ -152,9 +152,14 @@ SCA_API sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
 
 /* Differentiable split of sca_grad (a custom autograd backward): the
  * forward factorises every A_ns and keeps what the backward needs in the
- * caller's buffer `factors` of sca_factor_bytes(p) bytes; the backward then
- * reads it instead of factorising again.  phi must be unchanged between the
- * two calls. */
+ * caller's device buffer `factors` of sca_factor_bytes(p) bytes (0 for
+ * invalid params); the backward then reads it instead of factorising
+ * again.  phi and params must be the same in both calls.  On the FP64
+ * blocked path (L*L > 64) the backward inverts the factors in place, so a
+ * second sca_grad_from_factors on the same buffer returns SCA_EINVAL until
+ * sca_factorize refills it; the other paths leave the buffer reusable.  A
+ * buffer that sca_factorize did not fill for these params is refused with
+ * SCA_EINVAL. */
 SCA_API size_t sca_factor_bytes(const sca_params* p);
 SCA_API sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
                          void* factors, double* omega2);
@@ -179,6 +184,60 @@ SCA_API sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
 SCA_API sca_status sca_profile(sca_ctx* ctx, int enable);
 SCA_API sca_status sca_profile_read(sca_ctx* ctx, double* total_ms,
                                     int64_t* launches);
+
+/* Serving (the request loop of continuous batching).  A server owns its
+ * own HIP streams and device workspaces on `device` and runs many ADAM
+ * solves at once: requests of the same (L, n_max, precision) are evaluated
+ * together, one batched pass (every matrix of every member problem) per
+ * ADAM step, and shapes run concurrently on separate streams.  Each request
+ * keeps its own phi, moments, step counter and hyper-parameters on the
+ * device; its result equals that of sca_adam_solve on the same inputs, bit
+ * for bit, whatever else shared its batches.
+ *
+ * Admission: first come, first served per shape.  A shape's group takes up
+ * to max_batch problems; its workspace (the footprint of that many
+ * problems, fewer if the budget is short) must fit hbm_budget_bytes
+ * (0 = 90% of the device memory free at creation) together with the other
+ * groups; idle empty groups give their memory back when another shape
+ * needs it.  Requests wait in the queue until they fit.
+ *
+ * The caller owns phi, m, v (device arrays of L*L float64: phi holds phi0
+ * on submit and the solution when done; m, v the ADAM moments, zero for a
+ * fresh start) and must keep them alive and untouched until the request is
+ * done.  Work advances only inside sca_server_progress.  A server is not
+ * thread-safe.
+ *
+ *   sca_server_create   max_batch in [1, 4096]; SCA_EDEVICE if the device
+ *                       is absent or not gfx950.
+ *   sca_server_submit   validates like sca_adam_solve (grad_tol and
+ *                       check_every must be 0: requests run exactly
+ *                       n_steps updates, then, unless SCA_ADAM_NO_FINAL_EVAL,
+ *                       one evaluation at the returned phi); SCA_ENOMEM if
+ *                       one request alone exceeds the budget.  *ticket
+ *                       names the request.
+ *   sca_server_progress retires finished passes, admits queued requests
+ *                       and launches the next passes; with wait_s > 0 it
+ *                       waits up to that long for a pass to finish.
+ *                       Reports the running and queued request counts.
+ *   sca_server_poll     *done = 1 once the request finished; then *res
+ *                       (flags as for sca_adam_solve; a pivot growth above
+ *                       1e3 under FP32 is flagged, not re-run) and *t_done
+ *                       (sca_server_clock time the server saw it finish)
+ *                       are set and the ticket is released.
+ *   sca_server_clock    seconds since the server was created. */
+typedef struct sca_server sca_server;
+SCA_API sca_status sca_server_create(int device, size_t hbm_budget_bytes,
+                                     int32_t max_batch, sca_server** out);
+SCA_API void sca_server_destroy(sca_server* s);
+SCA_API double sca_server_clock(const sca_server* s);
+SCA_API sca_status sca_server_submit(sca_server* s, const sca_params* p,
+                                     const sca_adam_opts* o, double* phi,
+                                     double* m, double* v, int64_t* ticket);
+SCA_API sca_status sca_server_progress(sca_server* s, double wait_s,
+                                       int32_t* n_active, int32_t* n_queued);
+SCA_API sca_status sca_server_poll(sca_server* s, int64_t ticket,
+                                   int32_t* done, sca_result* res,
+                                   double* t_done);
 
 /* Message for the last error on this thread ("" if none). */
 SCA_API const char* sca_last_error(void);

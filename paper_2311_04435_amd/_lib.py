@@ -26,7 +26,9 @@ KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",
            "sca_grad", "sca_adam_solve", "sca_dos", "sca_shifted_terms",
            "sca_factor_bytes", "sca_factorize", "sca_grad_from_factors",
-           "sca_profile", "sca_profile_read", "sca_last_error")
+           "sca_profile", "sca_profile_read", "sca_server_create",
+           "sca_server_destroy", "sca_server_clock", "sca_server_submit",
+           "sca_server_progress", "sca_server_poll", "sca_last_error")
 
 
 class Params(C.Structure):
@@ -80,6 +82,15 @@ def _load():
         "sca_profile": (i32, [vp, C.c_int]),
         "sca_profile_read": (i32, [vp, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int64)]),
+        "sca_server_create": (i32, [C.c_int, C.c_size_t, i32, C.POINTER(vp)]),
+        "sca_server_destroy": (None, [vp]),
+        "sca_server_clock": (C.c_double, [vp]),
+        "sca_server_submit": (i32, [vp, P, O, dp, dp, dp,
+                                    C.POINTER(C.c_int64)]),
+        "sca_server_progress": (i32, [vp, C.c_double, C.POINTER(i32),
+                                      C.POINTER(i32)]),
+        "sca_server_poll": (i32, [vp, C.c_int64, C.POINTER(i32), R,
+                                  C.POINTER(C.c_double)]),
         "sca_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

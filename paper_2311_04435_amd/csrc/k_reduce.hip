@@ -83,7 +83,7 @@ struct ChunkPartial {
 __global__ void __launch_bounds__(kReduceThreads)
 site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
                    const double* __restrict__ dg, ChunkPartial* __restrict__ part,
-                   int adam_t, AdamHyper hy) {
+                   int adam) {
   const int p = blockIdx.y;
   const int chunk = blockIdx.x;
   const ProbDesc P = probs[p];
@@ -124,12 +124,13 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
       stag = (double)stagger_sign(i, P.L) * ph;
       ga = fabs(g);
       nf = !isfinite(g);
-      if (adam_t > 0 && dg) {
-        const double m = hy.beta1 * P.m[i] + (1.0 - hy.beta1) * g;
-        const double v = hy.beta2 * P.v[i] + (1.0 - hy.beta2) * g * g;
-        const double bc1 = 1.0 - pow(hy.beta1, (double)adam_t);
-        const double bc2 = 1.0 - pow(hy.beta2, (double)adam_t);
-        const double upd = hy.lr * (m / bc1) / (sqrt(v / bc2) + hy.eps);
+      if (adam && dg && P.steps_left > 0) {
+        const int t = P.adam_t + 1;
+        const double m = P.beta1 * P.m[i] + (1.0 - P.beta1) * g;
+        const double v = P.beta2 * P.v[i] + (1.0 - P.beta2) * g * g;
+        const double bc1 = 1.0 - pow(P.beta1, (double)t);
+        const double bc2 = 1.0 - pow(P.beta2, (double)t);
+        const double upd = P.lr * (m / bc1) / (sqrt(v / bc2) + P.eps);
         P.m[i] = m;
         P.v[i] = v;
         const double nphi = ph - upd;
@@ -159,11 +160,11 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
 }
 
 __global__ void __launch_bounds__(256)
-problem_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
+problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
                       const double* __restrict__ lad,
                       const double* __restrict__ growth,
                       const ChunkPartial* __restrict__ part, int nchunks,
-                      ProbStats* __restrict__ stats) {
+                      ProbStats* __restrict__ stats, int advance) {
   const int p = blockIdx.x;
   const ProbDesc P = probs[p];
   const int tid = threadIdx.x;
@@ -206,6 +207,11 @@ problem_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
     S.nonfinite = nf;
     S.pad_ = 0;
     stats[p] = S;
+    // the site kernel of this pass has read adam_t and steps_left already
+    if (advance && P.steps_left > 0) {
+      probs[p].adam_t = P.adam_t + 1;
+      probs[p].steps_left = P.steps_left - 1;
+    }
   }
 }
 
@@ -215,22 +221,23 @@ size_t reduce_workspace_bytes(int nprob) {
 
 int reduce_max_sites() { return kSitesPerBlock * kMaxChunks; }
 
-hipError_t launch_reduce(const ProbDesc* probs, int nprob, int N,
-                            const double* lad, const double* dg,
-                            const double* growth, ProbStats* stats, int adam_t,
-                            AdamHyper hyper, void* ws, hipStream_t st) {
+hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
+                         const double* dg, const double* growth,
+                         ProbStats* stats, bool adam, void* ws,
+                         hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
   const int nchunks = (N + kSitesPerBlock - 1) / kSitesPerBlock;
   if (nchunks > kMaxChunks) return hipErrorInvalidValue;
   ChunkPartial* part = static_cast<ChunkPartial*>(ws);
   mark_begin(K_REDUCE, st);
   hipLaunchKernelGGL(site_reduce_kernel, dim3(nchunks, nprob),
-                     dim3(kReduceThreads), 0, st, probs, N, dg, part, adam_t,
-                     hyper);
+                     dim3(kReduceThreads), 0, st, probs, N, dg, part,
+                     (int)adam);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(problem_reduce_kernel, dim3(nprob), dim3(256), 0, st,
-                     probs, N, lad, growth, part, nchunks, stats);
+                     probs, N, lad, growth, part, nchunks, stats,
+                     (int)(adam && dg != nullptr));
   mark_end(K_REDUCE, st);
   return hipGetLastError();
 }

@@ -18,11 +18,12 @@
 
 #include "../../include/sca.h"
 #include "sca_common.h"
+#include "sca_engine.h"
 #include "sca_kernels.h"
 #include "sca_profile.h"
 #include "sca_runtime.h"
 
-namespace {
+namespace sca {
 
 thread_local std::string g_err;
 
@@ -36,14 +37,9 @@ sca_status fail(sca_status s, const char* fmt, ...) {
   return s;
 }
 
-#define HIP_TRY(expr)                                                        \
-  do {                                                                       \
-    hipError_t e_ = (expr);                                                  \
-    if (e_ != hipSuccess)                                                    \
-      return fail(SCA_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+}  // namespace sca
 
-}  // namespace
+#define HIP_TRY SCA_HIP_TRY
 
 struct sca_ctx {
   int device = 0;
@@ -80,14 +76,8 @@ sca_status validate_params(const sca_params* p) {
   return SCA_OK;
 }
 
-}  // namespace sca
-
-using namespace sca;
-
-namespace {
-
-sca_status check_dev_ptr(const sca_ctx* ctx, const void* ptr, const char* name,
-                         bool allow_null = false) {
+sca_status check_device_ptr(int device, const void* ptr, const char* name,
+                            bool allow_null) {
   if (!ptr) {
     if (allow_null) return SCA_OK;
     return fail(SCA_EINVAL, "%s is NULL", name);
@@ -100,10 +90,59 @@ sca_status check_dev_ptr(const sca_ctx* ctx, const void* ptr, const char* name,
   }
   if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
     return fail(SCA_EINVAL, "%s is not device memory", name);
-  if (attr.device != ctx->device)
-    return fail(SCA_EINVAL, "%s lives on device %d, context on %d", name,
-                attr.device, ctx->device);
+  if (attr.device != device)
+    return fail(SCA_EINVAL, "%s lives on device %d, expected %d", name,
+                attr.device, device);
   return SCA_OK;
+}
+
+sca_status validate_adam_opts(const sca_adam_opts* o) {
+  if (!o) return fail(SCA_EINVAL, "opts is NULL");
+  if (o->n_steps < 0 || o->check_every < 0 || o->t0 < 0)
+    return fail(SCA_EINVAL, "n_steps, check_every, t0 must be >= 0");
+  if (o->flags & ~SCA_ADAM_NO_FINAL_EVAL)
+    return fail(SCA_EINVAL, "unknown ADAM flags 0x%x", o->flags);
+  if (!(o->lr > 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) ||
+      !(o->beta2 >= 0.0 && o->beta2 < 1.0) || !(o->eps >= 0.0) ||
+      !(o->grad_tol >= 0.0))
+    return fail(SCA_EINVAL, "invalid ADAM hyper-parameters");
+  return SCA_OK;
+}
+
+ProbDesc make_prob(const sca_params* p, const double* phi, double* grad) {
+  ProbDesc P{};
+  P.phi = phi;
+  P.onsite = p->onsite;
+  P.grad = grad;
+  P.t = p->t; P.U = p->U; P.delta = p->delta; P.T = p->T;
+  P.L = p->L; P.N = p->L * p->L; P.M = p->n_max;
+  P.mat_begin = 0;
+  P.hoff = 0;
+  return P;
+}
+
+hipError_t enqueue_pass(const Carve& c, int nprob, int L, int B,
+                        int precision, bool adam, hipStream_t st) {
+  const int N = L * L;
+  hipError_t e = launch_hvec(c.probs, nprob, N, c.hbuf, st);
+  if (e == hipSuccess)
+    e = factor_batch(c.descs, c.hbuf, B, N, L, precision, c.lad, c.dg,
+                     c.growth, c.fact, st);
+  if (e == hipSuccess)
+    e = launch_reduce(c.probs, nprob, N, c.lad, c.dg, c.growth, c.stats, adam,
+                      c.rws, st);
+  return e;
+}
+
+}  // namespace sca
+
+using namespace sca;
+
+namespace {
+
+sca_status check_dev_ptr(const sca_ctx* ctx, const void* ptr, const char* name,
+                         bool allow_null = false) {
+  return check_device_ptr(ctx->device, ptr, name, allow_null);
 }
 
 sca_status ensure_ws(sca_ctx* ctx, size_t bytes) {
@@ -162,35 +201,15 @@ struct DeviceGuard {
   }
 };
 
-ProbDesc make_prob(const sca_params* p, const double* phi, double* grad) {
-  ProbDesc P{};
-  P.phi = phi;
-  P.onsite = p->onsite;
-  P.grad = grad;
-  P.t = p->t; P.U = p->U; P.delta = p->delta; P.T = p->T;
-  P.L = p->L; P.N = p->L * p->L; P.M = p->n_max;
-  P.mat_begin = 0;
-  P.hoff = 0;
-  return P;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------- engine ----
 
 namespace sca {
 
-// Workspace carve-up for one batch of `nprob` problems of N sites with B
-// matrices in total.
-struct Carve {
-  ProbDesc* probs; MatDesc* descs; double* hbuf; double* lad; double* growth;
-  double* dg; void* rws; ProbStats* stats; void* fact;
-  size_t total;
-};
-
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-static Carve carve(char* base, int nprob, int N, int B, int precision,
+Carve carve(char* base, int nprob, int N, int B, int precision,
                    bool own_dg, bool own_lad, size_t fact_bytes) {
   Carve c{};
   size_t off = 0;
@@ -220,12 +239,14 @@ size_t footprint(int N, int M, int precision) {
 
 namespace {
 
-// Evaluate the terms of `nprob` problems (same L) already described in
-// host_probs; adam_t > 0 applies one fused ADAM update per problem.
-// If `descs_ready`, the descriptors in the workspace are reused.
+// Evaluate the terms of `nprob` problems (same L) described in host_probs;
+// with `adam`, every problem with steps left takes one fused ADAM update
+// (its counters advance on the device).  With `upload` the descriptors are
+// copied to the device first; otherwise the device copies (and counters)
+// of the previous pass are used.
 sca_status run_batch(sca_ctx* ctx, Carve& c, const ProbDesc* host_probs,
                      int nprob, int L, int B, int max2M, int precision,
-                     int adam_t, AdamHyper hy, bool upload) {
+                     bool adam, bool upload) {
   const int N = L * L;
   hipStream_t st = ctx->stream;
   if (upload) {
@@ -237,11 +258,8 @@ sca_status run_batch(sca_ctx* ctx, Carve& c, const ProbDesc* host_probs,
                            hipMemcpyHostToDevice, st));
     HIP_TRY(launch_matsubara_descs(c.probs, nprob, max2M, c.descs, st));
   }
-  HIP_TRY(launch_hvec(c.probs, nprob, N, c.hbuf, st));
-  HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, L, precision, c.lad, c.dg,
-                       c.growth, c.fact, st));
-  HIP_TRY(launch_reduce(c.probs, nprob, N, c.lad, c.dg, c.growth, c.stats,
-                        adam_t, hy, c.rws, st));
+  (void)N;
+  HIP_TRY(enqueue_pass(c, nprob, L, B, precision, adam, st));
   return SCA_OK;
 }
 
@@ -283,7 +301,7 @@ sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
   Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, true, true,
                   factor_workspace_bytes(N, B, p->precision));
   ProbDesc P = make_prob(p, phi, grad);
-  s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, 0, AdamHyper{}, true);
+  s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, false, true);
   if (s) return s;
   ProbStats S;
   s = read_stats(ctx, c, 1, &S);
@@ -384,14 +402,7 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
   if (s) return s;
   if (!o) return fail(SCA_EINVAL, "opts is NULL");
   if (!res) return fail(SCA_EINVAL, "result is NULL");
-  if (o->n_steps < 0 || o->check_every < 0 || o->t0 < 0)
-    return fail(SCA_EINVAL, "n_steps, check_every, t0 must be >= 0");
-  if (o->flags & ~SCA_ADAM_NO_FINAL_EVAL)
-    return fail(SCA_EINVAL, "unknown ADAM flags 0x%x", o->flags);
-  if (!(o->lr > 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) ||
-      !(o->beta2 >= 0.0 && o->beta2 < 1.0) || !(o->eps >= 0.0) ||
-      !(o->grad_tol >= 0.0))
-    return fail(SCA_EINVAL, "invalid ADAM hyper-parameters");
+  if ((s = validate_adam_opts(o))) return s;
   DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, m, "m"))) return s;
@@ -411,12 +422,14 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
   if ((s = setup())) return s;
   ProbDesc P = make_prob(p, phi, nullptr);
   P.m = m; P.v = v; P.phi_out = phi;
-  AdamHyper hy{o->lr, o->beta1, o->beta2, o->eps};
+  P.lr = o->lr; P.beta1 = o->beta1; P.beta2 = o->beta2; P.eps = o->eps;
+  P.adam_t = o->t0;
+  P.steps_left = o->n_steps;
   std::memset(res, 0, sizeof *res);
   int done = 0;
   bool converged = false, upload = true;
   for (int k = 1; k <= o->n_steps; ++k) {
-    s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, o->t0 + k, hy, upload);
+    s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, true, upload);
     if (s) return s;
     upload = false;
     done = k;
@@ -434,6 +447,8 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
         if (path_supported(N, SCA_FP64)) {
           prec = SCA_FP64;
           if ((s = setup())) return s;
+          P.adam_t = o->t0 + done;
+          P.steps_left = o->n_steps - done;
           upload = true;
         }
       }
@@ -449,7 +464,7 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
     if ((s = read_stats(ctx, c, 1, &S))) return s;
   } else {
     // statistics at the returned phi
-    s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, 0, hy, upload);
+    s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, false, upload);
     if (s) return s;
     if ((s = read_stats(ctx, c, 1, &S))) return s;
   }
@@ -562,15 +577,19 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
   c.fact = lay.fact;
   ProbDesc P = make_prob(p, phi, nullptr);
   hipStream_t st = ctx->stream;
-  if ((s = ensure_pinned(ctx, sizeof P))) return s;
+  if ((s = ensure_pinned(ctx, 512))) return s;
   HIP_TRY(hipStreamSynchronize(st));
   std::memcpy(ctx->pinned, &P, sizeof P);
+  FactorHeader* hh = reinterpret_cast<FactorHeader*>(
+      static_cast<char*>(ctx->pinned) + 256);
+  *hh = FactorHeader{kFactorsReady, p->L, p->n_max, p->precision};
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_matsubara_descs(c.probs, 1, B, c.descs, st));
   HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
   HIP_TRY(factor_forward(c.descs, c.hbuf, B, N, p->L, p->precision, c.lad,
                          c.dg, c.growth, c.fact, st));
   HIP_TRY(launch_reduce_omega(c.probs, 1, N, c.lad, c.growth, c.stats, c.rws, st));
+  HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice, st));
   ProbStats S;
   if ((s = read_stats(ctx, c, 1, &S))) return s;
   double o2[2] = {S.omega, S.omega_tilde};
@@ -597,13 +616,30 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
   AutogradLayout lay = autograd_layout(factors, N, B, p->precision);
   ProbDesc P = make_prob(p, phi, grad);
   hipStream_t st = ctx->stream;
-  if ((s = ensure_pinned(ctx, sizeof P))) return s;
+  if ((s = ensure_pinned(ctx, 512))) return s;
   HIP_TRY(hipStreamSynchronize(st));
+  FactorHeader* hh = reinterpret_cast<FactorHeader*>(
+      static_cast<char*>(ctx->pinned) + 256);
+  HIP_TRY(hipMemcpyAsync(hh, lay.head, sizeof *hh, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hh->state == kFactorsConsumed)
+    return fail(SCA_EINVAL, "factors were consumed by an earlier "
+                "sca_grad_from_factors (this path inverts them in place); "
+                "call sca_factorize again");
+  if (hh->state != kFactorsReady || hh->L != p->L || hh->n_max != p->n_max ||
+      hh->precision != p->precision)
+    return fail(SCA_EINVAL, "factors do not hold a factorisation of these "
+                "params (sca_factorize not called with them)");
   std::memcpy(ctx->pinned, &P, sizeof P);
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
   HIP_TRY(factor_backward(B, N, p->precision, lay.lad, lay.dg, lay.fact, st));
-  HIP_TRY(launch_reduce(c.probs, 1, N, lay.lad, lay.dg, lay.growth, c.stats, 0,
-                        AdamHyper{}, c.rws, st));
+  HIP_TRY(launch_reduce(c.probs, 1, N, lay.lad, lay.dg, lay.growth, c.stats,
+                        false, c.rws, st));
+  if (factor_backward_consumes(N, p->precision)) {
+    hh->state = kFactorsConsumed;
+    HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice,
+                           st));
+  }
   ProbStats S;
   if ((s = read_stats(ctx, c, 1, &S))) return s;
   if (S.nonfinite) return fail(SCA_ENUMERIC, "non-finite gradient");

@@ -28,9 +28,12 @@ struct ProbDesc {
   double* v;             // [N] ADAM second moment (adam only)
   double* phi_out;       // [N] updated field (adam only; may alias phi)
   double t, U, delta, T;
+  double lr, beta1, beta2, eps;   // ADAM hyper-parameters
   int32_t L, N, M;       // lattice side, sites, Matsubara count
   int32_t mat_begin;     // matrices [mat_begin, mat_begin + 2M): up then down
   int32_t hoff;          // h vectors: up at hoff, down at hoff + N
+  int32_t adam_t;        // ADAM updates applied so far (next uses adam_t + 1)
+  int32_t steps_left;    // updates still to apply; 0: evaluate only
   int32_t pad_;
 };
 

@@ -98,8 +98,13 @@ hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
   return blocked_inv_f64(p, B, N, bb.F, bb.perm, bb.tri, dg, st);
 }
 
+bool factor_backward_consumes(int N, int precision) {
+  return N > kSmallMax && precision == 0;
+}
+
 size_t autograd_factor_bytes(int N, int B, int precision) {
-  size_t bytes = align256(sizeof(double) * (size_t)B)        // lad
+  size_t bytes = align256(sizeof(FactorHeader))
+               + align256(sizeof(double) * (size_t)B)        // lad
                + align256(sizeof(double) * (size_t)B)        // growth
                + align256(sizeof(double) * 2 * (size_t)B * N)  // dg
                + factor_workspace_bytes(N, B, precision);   // LU factors
@@ -110,6 +115,8 @@ AutogradLayout autograd_layout(void* base, int N, int B, int precision) {
   (void)precision;
   char* p = static_cast<char*>(base);
   AutogradLayout a;
+  a.head = reinterpret_cast<FactorHeader*>(p);
+  p += align256(sizeof(FactorHeader));
   a.lad = reinterpret_cast<double*>(p);
   p += align256(sizeof(double) * (size_t)B);
   a.growth = reinterpret_cast<double*>(p);
@@ -162,11 +169,11 @@ hipError_t launch_make_shifts(const double* w, int n_w, double eta, double* z,
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_omega(const ProbDesc* probs, int nprob, int N,
+hipError_t launch_reduce_omega(ProbDesc* probs, int nprob, int N,
                                const double* lad, const double* growth,
                                ProbStats* stats, void* ws, hipStream_t st) {
-  return launch_reduce(probs, nprob, N, lad, nullptr, growth, stats, 0,
-                       AdamHyper{}, ws, st);
+  return launch_reduce(probs, nprob, N, lad, nullptr, growth, stats, false, ws,
+                       st);
 }
 
 }  // namespace sca

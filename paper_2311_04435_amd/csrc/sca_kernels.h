@@ -22,15 +22,17 @@ hipError_t launch_small_factor(const MatDesc* descs, const double* hbuf, int B,
                                double* growth, hipStream_t st);
 
 // Reduction of the per-matrix terms into Omega, Omega~ and the gradient of
-// every problem, optionally followed by one ADAM update (adam_t > 0 is the
-// 1-based step count used for the bias corrections).  stats[p] receives
-// Omega, Omega~, max|g|, |phi| (of the phi the terms were evaluated at) and
-// the largest pivot growth of the problem's matrices.
-struct AdamHyper { double lr, beta1, beta2, eps; };
-hipError_t launch_reduce(const ProbDesc* probs, int nprob, int N,
-                         const double* lad, const double* dg,
-                         const double* growth, ProbStats* stats, int adam_t,
-                         AdamHyper hyper, void* ws, hipStream_t st);
+// every problem.  With `adam` set (and dg given), every problem whose
+// steps_left is positive then takes one ADAM update with step count
+// adam_t + 1 and its own hyper-parameters, and the kernel advances that
+// problem's adam_t and steps_left in place; problems with steps_left == 0
+// are only evaluated.  stats[p] receives Omega, Omega~, max|g|, |phi| (of
+// the phi the terms were evaluated at) and the largest pivot growth of the
+// problem's matrices.
+hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
+                         const double* dg, const double* growth,
+                         ProbStats* stats, bool adam, void* ws,
+                         hipStream_t st);
 size_t reduce_workspace_bytes(int nprob);
 int reduce_max_sites();
 

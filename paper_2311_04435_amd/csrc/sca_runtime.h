@@ -26,9 +26,18 @@ hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
                         double* growth, void* fact, hipStream_t st);
 
 // Autograd split of factor_batch.  The forward writes lad and growth and
-// keeps in `fact` (and, for the fused small path, in dg) what the backward
-// needs; the backward completes dg from it.
-struct AutogradLayout { double* lad; double* growth; double* dg; void* fact; };
+// keeps in `fact` (and, for the fused small path and the FP32 route, in dg)
+// what the backward needs; the backward completes dg from it.  The buffer
+// starts with a header naming the problem shape and whether the factors are
+// still usable: the FP64 blocked backward inverts them in place.
+struct FactorHeader { uint32_t state; int32_t L, n_max, precision; };
+constexpr uint32_t kFactorsReady = 0x5CA10001u;
+constexpr uint32_t kFactorsConsumed = 0x5CA10002u;
+struct AutogradLayout {
+  FactorHeader* head; double* lad; double* growth; double* dg; void* fact;
+};
+// Whether factor_backward overwrites the factors it reads.
+bool factor_backward_consumes(int N, int precision);
 size_t autograd_factor_bytes(int N, int B, int precision);
 AutogradLayout autograd_layout(void* base, int N, int B, int precision);
 hipError_t factor_forward(const MatDesc* descs, const double* hbuf, int B,
@@ -38,7 +47,7 @@ hipError_t factor_backward(int B, int N, int precision, const double* lad,
                            double* dg, void* fact, hipStream_t st);
 
 // Omega, Omega~ of every problem without the gradient (dg not read).
-hipError_t launch_reduce_omega(const ProbDesc* probs, int nprob, int N,
+hipError_t launch_reduce_omega(ProbDesc* probs, int nprob, int N,
                                const double* lad, const double* growth,
                                ProbStats* stats, void* ws, hipStream_t st);
 

@@ -41,6 +41,17 @@ def uniform(seed: int, count: int, lo: float, hi: float) -> np.ndarray:
     return lo + (hi - lo) * u
 
 
+def rademacher(seed: int, count: int) -> np.ndarray:
+    """`count` independent +-1.0 values (bit 63 of each SplitMix64 output)."""
+    return np.where(splitmix64(seed, count) >> np.uint64(63), -1.0, 1.0)
+
+
+def sample_indices(seed: int, n: int, k: int) -> np.ndarray:
+    """k distinct indices in [0, n): the first k of a seeded permutation."""
+    keys = splitmix64(seed, n)
+    return np.argsort(keys, kind="stable")[:k]
+
+
 def stagger(L: int) -> np.ndarray:
     """(-1)^(x+y) for site i = x + L*y, as float64 (a lattice sign pattern)."""
     x = np.arange(L * L) % L

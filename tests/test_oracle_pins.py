@@ -14,6 +14,7 @@ import scipy.linalg
 import oracle
 from oracle import closed
 from oracle.lu import lu_pivoted, logabsdet_lu, inverse_lu, leibniz_det, adjugate_diag
+import synth
 from synth import uniform
 
 
@@ -336,3 +337,25 @@ def test_adam_reaches_neel_state():
     m = closed.neel_m(L, 1.0, U, 0.0, T, M)
     assert abs(oracle.af_order(phi, L) - m) < 1e-6
     assert np.max(np.abs(phi - m * s)) < 1e-5
+
+
+def test_oracle_grad_matches_stored_finite_differences():
+    """The oracle's gradient (route S) against the central differences of its
+    own Omega~ stored by tests/golden/make_fd_grad.py (32x32 ionic lattice,
+    16 fields, 4 Rademacher + 8 coordinate directions each)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "fd_grad_32x32.json")
+    with open(path) as f:
+        gold = json.load(f)
+    N = gold["L"] ** 2
+    for case in gold["cases"][::4]:
+        phi = synth.uniform(case["seed"], N, -0.5, 0.5)
+        g = oracle.grad(case["params"], phi)
+        for d in case["directions"]:
+            if d["kind"] == "coord":
+                gd = g[d["arg"]]
+            else:
+                gd = float(g @ synth.rademacher(d["arg"], N))
+            assert abs(gd - d["fd"]) <= 10 * case["floor"] + 1e-7 * abs(d["fd"])
