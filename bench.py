@@ -13,7 +13,11 @@ Prints one JSON line.  Besides the contract fields it carries
   roofline      the dominant kernel's achieved rate against the MI355X peak,
                 from HIP events on the library's stream over a second,
                 profiled run of the same steps;
-  cpu_baseline  the FP64 oracle timed on this host on a bounded sample.
+  cpu_baseline  the FP64 oracle timed on this host on a bounded sample;
+  l32           steps/s of the 32x32 ionic lattice in both precisions;
+  serving       served solves/s and p50/p99 latency of a Poisson stream of
+                mixed requests through the request server, next to the
+                one-at-a-time FIFO baseline on the same GPU.
 """
 from __future__ import annotations
 
@@ -97,6 +101,82 @@ def cpu_baseline(wl, budget_s: float):
             "route_s_steps_per_s": route_s}
 
 
+def workload_rate(sca, name, prec, steps, warmup):
+    """Timed ADAM steps of a named workload (phi, m, v resident on the GPU)."""
+    import torch
+    import synth
+    wl = synth.WORKLOADS[name]
+    p = sca.Params.from_dict(wl["params"], precision=prec)
+    hy = wl["adam"]
+    phi = torch.as_tensor(synth.make_phi0(p.L, wl["phi0"]),
+                          dtype=torch.float64).cuda()
+    m, v = torch.zeros_like(phi), torch.zeros_like(phi)
+    ctx = sca.Context()
+    kw = dict(lr=hy["lr"], beta1=hy["beta1"], beta2=hy["beta2"], eps=hy["eps"],
+              final_eval=False)
+    ctx.adam_solve(p, phi, m, v, warmup, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.adam_solve(p, phi, m, v, steps, t0=warmup, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": name, "precision": prec, "steps": steps,
+            "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps}
+
+
+def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0):
+    """Poisson stream of mixed requests: one at a time (FIFO, measured
+    service times) vs the request server (real time)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2311_04435_amd.serve import (Server, run_stream, fifo_latencies,
+                                            latency_summary)
+    reqs = []
+    for r in synth.serving_stream(n_req, seed, n_max, Ls=Ls):
+        p = sca.Params.from_dict(r["params"])
+        phi0 = torch.as_tensor(synth.make_phi0(p.L, r["phi0"]),
+                               dtype=torch.float64).cuda()
+        reqs.append(dict(params=p, phi0=phi0, n_steps=steps))
+    # warm every shape once (code objects, workspaces)
+    ctx = sca.default_context()
+    for L in sorted({r["params"].L for r in reqs}):
+        r = next(q for q in reqs if q["params"].L == L)
+        sca.adam_solve(r["params"], r["phi0"], 1)
+    service, alone = [], []
+    for r in reqs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = sca.adam_solve(r["params"], r["phi0"], r["n_steps"])
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        alone.append(out[0])
+    service = np.array(service)
+    print(f"bench: serving, one-at-a-time pass {service.sum():.1f} s",
+          file=sys.stderr, flush=True)
+    rate = load * len(reqs) / service.sum()
+    arrivals = synth.poisson_arrivals(seed + 17, len(reqs), rate)
+    fifo_lat, fifo_span = fifo_latencies(arrivals, service)
+    with Server(max_batch=max_batch) as srv:
+        # warm the server's groups with one short solve per shape
+        warm = [srv.submit(r["params"], r["phi0"], 1)
+                for r in {q["params"].L: q for q in reqs}.values()]
+        srv.drain(warm)
+        results, lat, span = run_stream(srv, reqs, arrivals)
+    print(f"bench: serving, served pass {span:.1f} s", file=sys.stderr,
+          flush=True)
+    same = all(torch.equal(results[k][0], alone[k]) for k in range(len(reqs)))
+    del ctx
+    return {"workload": (f"{n_req} requests, L in {sorted(set(Ls))}, "
+                         f"n_max={n_max}, {steps} ADAM steps each, FP64, "
+                         f"U~U[2,8], Delta~U[0,2], T~U[0.05,0.6]"),
+            "arrivals": f"Poisson, {rate:.3f}/s = {load} x FIFO capacity",
+            "max_batch": max_batch,
+            "served": latency_summary(lat, span),
+            "fifo_one_at_a_time": latency_summary(fifo_lat, fifo_span),
+            "alone_vs_mix_bitwise": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +186,13 @@ def main():
     ap.add_argument("--precision", default=None, help="fp64 | fp32r")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-l32", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=32,
+                    help="0 skips the serving measurement")
+    ap.add_argument("--serving-steps", type=int, default=200)
+    ap.add_argument("--serving-nmax", type=int, default=256)
+    ap.add_argument("--serving-L", default="8,12,16,20")
+    ap.add_argument("--serving-batch", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
@@ -192,6 +279,13 @@ def main():
                   "max_abs_grad": res["max_abs_grad"],
                   "max_pivot_growth": res["max_pivot_growth"]},
     }
+    if not args.no_l32:
+        out["l32"] = [workload_rate(sca, "ionic_32x32_U4", "fp32r", 5, 1),
+                      workload_rate(sca, "ionic_32x32_U4", "fp64", 3, 1)]
+    if args.serving_requests > 0:
+        Ls = tuple(int(x) for x in args.serving_L.split(","))
+        out["serving"] = serving(sca, args.serving_requests, args.serving_steps,
+                                 args.serving_nmax, Ls, args.serving_batch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -195,8 +195,10 @@ SCA_API sca_status sca_profile_read(sca_ctx* ctx, double* total_ms,
  * for bit, whatever else shared its batches.
  *
  * Admission: first come, first served per shape.  A shape's group takes up
- * to max_batch problems; its workspace (the footprint of that many
- * problems, fewer if the budget is short) must fit hbm_budget_bytes
+ * to max_batch problems, fewer for large lattices (as many as keep one pass
+ * near 3e10 flops of factorisation work, at least one: past that a bigger
+ * batch adds latency, not throughput); its workspace (the footprint of that
+ * many problems, fewer if the budget is short) must fit hbm_budget_bytes
  * (0 = 90% of the device memory free at creation) together with the other
  * groups; idle empty groups give their memory back when another shape
  * needs it.  Requests wait in the queue until they fit.

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -37,6 +38,20 @@ namespace {
 
 constexpr double kChunkTargetMs = 2.0;   // aim of one chunk of passes
 constexpr int kMaxChunk = 64;
+
+// Batching more problems into one pass only pays while a pass is short
+// (launch- and latency-bound): every matrix already has a workgroup of its
+// own, so once one problem fills the GPU a bigger batch only makes all of
+// its members wait for each other.  A group therefore takes as many
+// problems as keep one pass near kPassFlops of factorisation work (about
+// 2 ms at the rate the FP64 kernels reach on these sizes), at least one.
+constexpr double kPassFlops = 3e10;
+
+int group_cap(int N, int M, int max_batch) {
+  const double per_problem = 2.0 * M * (16.0 / 3.0) * (double)N * N * N;
+  const double cap = std::floor(kPassFlops / per_problem);
+  return (int)std::max(1.0, std::min((double)max_batch, cap));
+}
 
 struct Group;
 
@@ -147,7 +162,7 @@ sca_status new_group(sca_server* s, const Request* r, Group** out) {
   auto fits = [&](int cap) {
     return s->used + group_bytes(N, M, prec, cap) <= s->budget;
   };
-  int cap = s->max_batch;
+  int cap = group_cap(N, M, s->max_batch);
   if (!fits(cap)) make_room(s, group_bytes(N, M, prec, cap));
   while (cap > 1 && !fits(cap)) cap /= 2;
   if (!fits(cap)) return SCA_OK;   // wait until a group frees its memory

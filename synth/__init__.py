@@ -112,19 +112,28 @@ def make_phi0(L: int, recipe: dict) -> np.ndarray:
     raise ValueError(f"unknown phi0 recipe {recipe['kind']!r}")
 
 
-def serving_stream(n_requests: int = 256, seed: int = 0, n_max: int = 256):
+def serving_stream(n_requests: int = 256, seed: int = 0, n_max: int = 256,
+                   Ls=(8, 12, 16, 20, 24, 32)):
     """A stream of SCA solve requests with mixed lattice sizes and couplings.
 
-    L uniform in {8,12,16,20,24,32}, U/t ~ U[2,8], Delta/t ~ U[0,2],
-    T/t ~ U[0.05,0.6]; phi0 ~ U[-0.5,0.5] seeded by the request id.
+    L uniform over Ls (default {8,12,16,20,24,32}), U/t ~ U[2,8],
+    Delta/t ~ U[0,2], T/t ~ U[0.05,0.6]; phi0 ~ U[-0.5,0.5] seeded by the
+    request id.
     """
-    Ls = np.array([8, 12, 16, 20, 24, 32])
+    Ls = np.asarray(Ls)
     r = uniform(seed, 4 * n_requests, 0.0, 1.0).reshape(n_requests, 4)
     out = []
     for k in range(n_requests):
-        L = int(Ls[min(int(r[k, 0] * 6), 5)])
+        L = int(Ls[min(int(r[k, 0] * len(Ls)), len(Ls) - 1)])
         out.append(dict(id=k, params=dict(
             L=L, t=1.0, U=2.0 + 6.0 * r[k, 1], delta=2.0 * r[k, 2],
             T=0.05 + 0.55 * r[k, 3], n_max=n_max),
             phi0=dict(kind="uniform", amp=0.5, seed=1000 + k)))
     return out
+
+
+def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
+    """Arrival times (from 0) of a Poisson process of the given rate:
+    cumulative sums of exponential gaps -ln(1 - u) / rate."""
+    u = uniform(seed, count, 0.0, 1.0)
+    return np.cumsum(-np.log1p(-u) / rate) - (-np.log1p(-u[0]) / rate)
