@@ -35,6 +35,27 @@ METRIC = ("ADAM steps/s (logdet+grad, all ω_n,σ) at L=20,32; "
 PEAK = {"fp64": 78.6, "fp32": 157.3}   # dense MFMA TFLOP/s, MI355X
 HBM_PEAK = 8000.0                       # GB/s
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled
+# by the same counters on a copy kernel of known size (read x 2.0, write x
+# 1.0); profiles/lu_f64_hubbard_20x20.md has the runs.  Keyed by (kernel
+# class, workload, precision) with the SHA-256 of the kernel source the
+# counters were taken on: a changed source reports null.
+TRAFFIC = {
+    ("lu", "hubbard_20x20_T0.1", "fp64"): (
+        15.912e9, "c42cf787c0f4f1d6a2ba316ca8ac08268c35ecaa959c32ca766554db2774947a"),
+}
+TRAFFIC_SRC = os.path.join(ROOT, "paper_2311_04435_amd", "csrc", "k_factor.hip")
+
+
+def measured_traffic(kernel: str, workload: str, prec: str):
+    import hashlib
+    hit = TRAFFIC.get((kernel, workload, prec))
+    if hit is None:
+        return None
+    with open(TRAFFIC_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return hit[0] if sha == hit[1] else None
+
 
 def kernel_work(kind: str, N: int, B: int):
     """Algorithmic work of one launch: (amount, unit, bound)."""
@@ -193,6 +214,9 @@ def main():
     ap.add_argument("--serving-nmax", type=int, default=256)
     ap.add_argument("--serving-L", default="8,12,16,20")
     ap.add_argument("--serving-batch", type=int, default=16)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times), "
+                         "the reference for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
@@ -202,6 +226,19 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)     # reads 4n bytes, writes 4n bytes
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_read_bytes": 4 * n, "copy_write_bytes": 4 * n,
+                          "launches": 3}), flush=True)
+        return
+
     import paper_2311_04435_amd as sca
     import synth
 
@@ -253,13 +290,14 @@ def main():
             achieved = amount / avg_s / 1e12
             roof = {"bound": "mfma", "kernel": dom, "achieved": achieved,
                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                    "traffic": None,
+                    "traffic": measured_traffic(dom, args.workload, prec),
                     "work_per_launch": f"{B} matrices x {amount / B:.4g} flop"}
         else:
             achieved = amount / avg_s / 1e9
             roof = {"bound": "hbm", "kernel": dom, "achieved": achieved,
                     "peak": HBM_PEAK, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK, "traffic": None,
+                    "frac": achieved / HBM_PEAK,
+                    "traffic": measured_traffic(dom, args.workload, prec),
                     "work_per_launch": f"{amount:.4g} bytes"}
 
     out = {
