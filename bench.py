@@ -38,18 +38,18 @@ HBM_PEAK = 8000.0                       # GB/s
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled
 # by the same counters on a copy kernel of known size (read x 2.0, write x
 # 1.0); profiles/lu_f64_hubbard_20x20.md has the runs.  Keyed by (kernel
-# class, workload, precision) with the SHA-256 of the kernel source the
+# class, workload, precision, factorisation) with the SHA-256 of the kernel source the
 # counters were taken on: a changed source reports null.
 TRAFFIC = {
-    ("lu", "hubbard_20x20_T0.1", "fp64"): (
+    ("lu", "hubbard_20x20_T0.1", "fp64", "lu"): (
         15.912e9, "c42cf787c0f4f1d6a2ba316ca8ac08268c35ecaa959c32ca766554db2774947a"),
 }
 TRAFFIC_SRC = os.path.join(ROOT, "paper_2311_04435_amd", "csrc", "k_factor.hip")
 
 
-def measured_traffic(kernel: str, workload: str, prec: str):
+def measured_traffic(kernel: str, workload: str, prec: str, factor: str):
     import hashlib
-    hit = TRAFFIC.get((kernel, workload, prec))
+    hit = TRAFFIC.get((kernel, workload, prec, factor))
     if hit is None:
         return None
     with open(TRAFFIC_SRC, "rb") as f:
@@ -64,6 +64,10 @@ def kernel_work(kind: str, N: int, B: int):
         return B * 8.0 / 3.0 * n3, "flop", "mfma"
     if kind == "trtri":       # U^-1 and L^-1: 2 x (4/3) N^3
         return B * 8.0 / 3.0 * n3, "flop", "mfma"
+    if kind == "ldlt":        # A = L D L^T, complex symmetric: (4/3) N^3
+        return B * 4.0 / 3.0 * n3, "flop", "mfma"
+    if kind == "trtri_sym":   # L^-T alone: (4/3) N^3
+        return B * 4.0 / 3.0 * n3, "flop", "mfma"
     if kind == "small":       # fused LU + both triangular inverses
         return B * 16.0 / 3.0 * n3, "flop", "mfma"
     if kind == "wvgemm":      # X = W V, upper x unit lower: (8/3) N^3
@@ -72,6 +76,8 @@ def kernel_work(kind: str, N: int, B: int):
         return B * 16.0 * N * N, "byte", "hbm"
     if kind == "diagdot":     # reads the W and V triangles once
         return B * 16.0 * N * N, "byte", "hbm"
+    if kind == "symdiag":     # reads the L^-T triangle once
+        return B * 8.0 * N * N, "byte", "hbm"
     if kind == "reduce":      # reads diag(A^-1) of every matrix
         return B * 16.0 * N, "byte", "hbm"
     return None
@@ -122,12 +128,12 @@ def cpu_baseline(wl, budget_s: float):
             "route_s_steps_per_s": route_s}
 
 
-def workload_rate(sca, name, prec, steps, warmup):
+def workload_rate(sca, name, prec, steps, warmup, factor="lu"):
     """Timed ADAM steps of a named workload (phi, m, v resident on the GPU)."""
     import torch
     import synth
     wl = synth.WORKLOADS[name]
-    p = sca.Params.from_dict(wl["params"], precision=prec)
+    p = sca.Params.from_dict(wl["params"], precision=prec, factor=factor)
     hy = wl["adam"]
     phi = torch.as_tensor(synth.make_phi0(p.L, wl["phi0"]),
                           dtype=torch.float64).cuda()
@@ -141,7 +147,8 @@ def workload_rate(sca, name, prec, steps, warmup):
     ctx.adam_solve(p, phi, m, v, steps, t0=warmup, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"workload": name, "precision": prec, "steps": steps,
+    return {"workload": name, "precision": prec, "factor": factor,
+            "steps": steps,
             "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps}
 
 
@@ -205,6 +212,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="hubbard_20x20_T0.1")
     ap.add_argument("--precision", default=None, help="fp64 | fp32r")
+    ap.add_argument("--factor", default="lu",
+                    help="lu (pivoted, default) | ldlt (symmetric, unpivoted)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-l32", action="store_true")
@@ -244,7 +253,7 @@ def main():
 
     wl = synth.WORKLOADS[args.workload]
     prec = args.precision or wl.get("precision", "fp64")
-    p = sca.Params.from_dict(wl["params"], precision=prec)
+    p = sca.Params.from_dict(wl["params"], precision=prec, factor=args.factor)
     L, M = p.L, p.n_max
     N, B = L * L, 2 * M
     phi0 = torch.as_tensor(synth.make_phi0(L, wl["phi0"]),
@@ -290,14 +299,16 @@ def main():
             achieved = amount / avg_s / 1e12
             roof = {"bound": "mfma", "kernel": dom, "achieved": achieved,
                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                    "traffic": measured_traffic(dom, args.workload, prec),
+                    "traffic": measured_traffic(dom, args.workload, prec,
+                                                args.factor),
                     "work_per_launch": f"{B} matrices x {amount / B:.4g} flop"}
         else:
             achieved = amount / avg_s / 1e9
             roof = {"bound": "hbm", "kernel": dom, "achieved": achieved,
                     "peak": HBM_PEAK, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK,
-                    "traffic": measured_traffic(dom, args.workload, prec),
+                    "traffic": measured_traffic(dom, args.workload, prec,
+                                                args.factor),
                     "work_per_launch": f"{amount:.4g} bytes"}
 
     out = {
@@ -309,6 +320,7 @@ def main():
         "data": "synthetic (seeded SplitMix64 phi0; lattice Hamiltonian generated on chip)",
         "config": {"workload": args.workload, "L": L, "N": N, "n_max": M,
                    "matrices_per_step": B, "precision": prec,
+                   "factor": args.factor,
                    "U": p.U, "T": p.T, "delta": p.delta,
                    "parallelism": "single GPU, batch of (w_n, spin) matrices"},
         "roofline": roof,

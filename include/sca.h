@@ -61,10 +61,22 @@ typedef enum {
   SCA_ENOMEM = -2,       /* workspace would exceed the context's HBM budget */
   SCA_EDEVICE = -3,      /* HIP runtime error or no usable gfx950 device */
   SCA_ENUMERIC = -4,     /* non-finite Omega/gradient/phi or a singular matrix */
-  SCA_EUNSUPPORTED = -5  /* size/precision combination not built */
+  SCA_EUNSUPPORTED = -5  /* size/precision/factor combination not built */
 } sca_status;
 
 typedef enum { SCA_FP64 = 0, SCA_FP32_REFINED = 1 } sca_precision;
+
+/* Factorisation of each A = z I - H (lattices with L*L > 64; smaller ones
+ * always use the fused pivoted LU).
+ *   SCA_FACTOR_LU    complex LU with partial pivoting (the default).
+ *   SCA_FACTOR_LDLT  A is complex symmetric: A = L D L^T without pivoting,
+ *                    half the flops and one triangular inverse instead of
+ *                    two.  Exists and is stable for Im z > 0 (every shift
+ *                    used here); each matrix whose growth max(max|D L^T| /
+ *                    max|A|, max|L|) exceeds 64 or whose pivots are not
+ *                    finite is redone by the pivoted LU on the device.
+ *                    FP64 only (SCA_EUNSUPPORTED with SCA_FP32_REFINED). */
+typedef enum { SCA_FACTOR_LU = 0, SCA_FACTOR_LDLT = 1 } sca_factor;
 
 /* One SCA problem.  onsite: optional DEVICE array of N extra site
  * potentials (a disordered lattice), or NULL (the paper's ionic model). */
@@ -72,7 +84,7 @@ typedef struct {
   int32_t L;          /* even, 2 <= L <= 64 */
   int32_t n_max;      /* M >= 1 */
   int32_t precision;  /* sca_precision */
-  int32_t reserved;   /* must be 0 */
+  int32_t factor;     /* sca_factor */
   double t, U, delta, T;
   const double* onsite;
 } sca_params;
@@ -172,7 +184,7 @@ SCA_API sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
  * stream; sca_profile(ctx, 0) stops.  sca_profile_read fills HOST arrays of
  * SCA_PROFILE_SLOTS entries with the accumulated milliseconds and launch
  * counts per kernel class (SCA_K_*). */
-#define SCA_PROFILE_SLOTS 8
+#define SCA_PROFILE_SLOTS 16
 #define SCA_K_SMALL 0   /* fused small-lattice factor + inverse diagonal */
 #define SCA_K_LU 1      /* blocked LU with partial pivoting */
 #define SCA_K_TRTRI 2   /* blocked U^-1 and L^-1 */
@@ -181,6 +193,10 @@ SCA_API sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
 #define SCA_K_SETUP 5   /* descriptors and diagonal vectors */
 #define SCA_K_REFINE 6  /* FP64 refinement of the FP32 route */
 #define SCA_K_WVGEMM 7  /* X = U^-1 L^-1 product of the FP32 route */
+#define SCA_K_LDLT 8    /* symmetric route: L D L^T */
+#define SCA_K_TRTRI_SYM 9  /* symmetric route: L^-T */
+#define SCA_K_SYMDIAG 10   /* symmetric route: diagonal of A^-1 */
+#define SCA_K_FALLBACK 11  /* symmetric route: pivoted LU of flagged matrices */
 SCA_API sca_status sca_profile(sca_ctx* ctx, int enable);
 SCA_API sca_status sca_profile_read(sca_ctx* ctx, double* total_ms,
                                     int64_t* launches);

@@ -24,14 +24,17 @@ from ._lib import (SCAError, SCA_FP64, SCA_FP32_REFINED,  # noqa: F401
                    SCA_FLAG_CONVERGED)
 
 PRECISIONS = {"fp64": SCA_FP64, "fp32r": SCA_FP32_REFINED}
+FACTORS = {"lu": _lib.SCA_FACTOR_LU, "ldlt": _lib.SCA_FACTOR_LDLT}
 
 
 @dataclasses.dataclass(frozen=True)
 class Params:
     """One SCA problem: L x L lattice (L even), hopping t, on-site U > 0,
     ionic amplitude delta (site potential +-delta/2), temperature T > 0,
-    n_max Matsubara frequencies per sign, precision 'fp64' | 'fp32r', and an
-    optional extra site potential `onsite` (float64 CUDA tensor of N)."""
+    n_max Matsubara frequencies per sign, precision 'fp64' | 'fp32r',
+    factorisation 'lu' (pivoted, default) | 'ldlt' (symmetric, unpivoted,
+    FP64) and an optional extra site potential `onsite` (float64 CUDA tensor
+    of N)."""
     L: int
     U: float
     T: float
@@ -40,6 +43,7 @@ class Params:
     delta: float = 0.0
     precision: str = "fp64"
     onsite: Optional[torch.Tensor] = None
+    factor: str = "lu"
 
     @property
     def N(self) -> int:
@@ -48,11 +52,14 @@ class Params:
     def c(self) -> _lib.Params:
         if self.precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        if self.factor not in FACTORS:
+            raise ValueError(f"factor must be one of {list(FACTORS)}")
         ons = None
         if self.onsite is not None:
             ons = _dev(self.onsite, self.N, "onsite").data_ptr()
-        return _lib.Params(self.L, self.n_max, PRECISIONS[self.precision], 0,
-                           self.t, self.U, self.delta, self.T, ons)
+        return _lib.Params(self.L, self.n_max, PRECISIONS[self.precision],
+                           FACTORS[self.factor], self.t, self.U, self.delta,
+                           self.T, ons)
 
     @classmethod
     def from_dict(cls, d: dict, precision: str = "fp64", **kw) -> "Params":

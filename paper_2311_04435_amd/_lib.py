@@ -16,11 +16,13 @@ SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EDEVICE, SCA_ENUMERIC, SCA_EUNSUPPORTED = \
 STATUS_NAMES = {0: "SCA_OK", -1: "SCA_EINVAL", -2: "SCA_ENOMEM",
                 -3: "SCA_EDEVICE", -4: "SCA_ENUMERIC", -5: "SCA_EUNSUPPORTED"}
 SCA_FP64, SCA_FP32_REFINED = 0, 1
+SCA_FACTOR_LU, SCA_FACTOR_LDLT = 0, 1
 SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH, SCA_FLAG_CONVERGED = 1, 2, 4
 SCA_ADAM_NO_FINAL_EVAL = 1
-PROFILE_SLOTS = 8
+PROFILE_SLOTS = 16
 KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
-                  "refine", "wvgemm")
+                  "refine", "wvgemm", "ldlt", "trtri_sym", "symdiag",
+                  "fallback", "spare12", "spare13", "spare14", "spare15")
 
 # Every symbol include/sca.h declares.
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",
@@ -33,7 +35,7 @@ EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",
 
 class Params(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_max", C.c_int32),
-                ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("precision", C.c_int32), ("factor", C.c_int32),
                 ("t", C.c_double), ("U", C.c_double), ("delta", C.c_double),
                 ("T", C.c_double), ("onsite", C.c_void_p)]
 

@@ -22,38 +22,12 @@
 #include <math.h>
 #include "sca_common.h"
 #include "sca_blocked.h"
+#include "k_factor_common.h"
 #include "sca_profile.h"
 
 namespace sca {
 
 namespace {
-
-// MFMA of the element type: 16x16x4, A[m][k] from lane (k<<4 | m), B[k][n]
-// from lane (k<<4 | n); accumulator element i of lane (g<<4 | n) holds row
-// m(g, i) of column n (f64: g + 4i, f32: 4g + i, as measured on gfx950).
-template <typename T> struct Mma;
-template <> struct Mma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mma(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int m(int g, int i) { return g + 4 * i; }
-};
-template <> struct Mma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mma(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int m(int g, int i) { return 4 * g + i; }
-};
-
-__device__ inline void argmax_wave(double& mag, int& row) {
-  for (int off = 32; off >= 1; off >>= 1) {
-    double om = __shfl_xor(mag, off);
-    int orow = __shfl_xor(row, off);
-    if (om > mag || (om == mag && orow < row)) { mag = om; row = orow; }
-  }
-}
 
 template <typename T, int NB>
 struct LuLds {
@@ -69,8 +43,6 @@ struct LuLds {
   T *tr_, *ti_;       // [NB*NB/2] scratch of the block inversion
   double* red;        // [NT] final reductions
 };
-
-constexpr int LD(int NB) { return NB + 1; }
 
 }  // namespace
 
@@ -88,135 +60,13 @@ size_t lu_lds_bytes(int Np, int NB, int waves) {
   return b + 256;
 }
 
-namespace {
-
-__device__ inline double readlane_d(double v, int lane) {
-  const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Inverses of the unit lower and the upper triangle of the NB x NB block
-// (xr, xi; leading dimension NB+1), by recursive doubling: 4x4 leaves by
-// one thread each, then for s = 8, 16, .. NB
-//   [A 0; C D]^-1 = [A^-1 0; -D^-1 C A^-1  D^-1]
-//   [A B; 0 D]^-1 = [A^-1  -A^-1 B D^-1; 0 D^-1]
-// with the products spread over all threads.  Outputs carry explicit zeros
-// and the unit diagonal of L^-1.
-template <typename T, int NB, int NT>
-__device__ void block_tri_inverses(const T* xr, const T* xi, T* lr, T* li,
-                                   T* ur, T* ui, T* tr, T* ti, int tid) {
-  constexpr int LDB = NB + 1;
-  for (int e = tid; e < NB * NB; e += NT) {
-    const int r = e / NB, c = e % NB;
-    lr[r * LDB + c] = 0.0; li[r * LDB + c] = 0.0;
-    ur[r * LDB + c] = 0.0; ui[r * LDB + c] = 0.0;
-  }
-  __syncthreads();
-  constexpr int NLEAF = NB / 4;
-  if (tid < 2 * NLEAF) {
-    const int o = 4 * (tid % NLEAF);
-    if (tid < NLEAF) {
-      for (int c = 0; c < 4; ++c) {
-        lr[(o + c) * LDB + o + c] = 1.0;
-        for (int r = c + 1; r < 4; ++r) {
-          double sr = xr[(o + r) * LDB + o + c], si = xi[(o + r) * LDB + o + c];
-          for (int k = c + 1; k < r; ++k) {
-            const double ar = xr[(o + r) * LDB + o + k], ai = xi[(o + r) * LDB + o + k];
-            const double br = lr[(o + k) * LDB + o + c], bi = li[(o + k) * LDB + o + c];
-            sr += ar * br - ai * bi;
-            si += ar * bi + ai * br;
-          }
-          lr[(o + r) * LDB + o + c] = -sr;
-          li[(o + r) * LDB + o + c] = -si;
-        }
-      }
-    } else {
-      for (int c = 0; c < 4; ++c) {
-        for (int r = c; r >= 0; --r) {
-          double sr = (r == c) ? 1.0 : 0.0, si = 0.0;
-          for (int k = r + 1; k <= c; ++k) {
-            const double ar = xr[(o + r) * LDB + o + k], ai = xi[(o + r) * LDB + o + k];
-            const double br = ur[(o + k) * LDB + o + c], bi = ui[(o + k) * LDB + o + c];
-            sr -= ar * br - ai * bi;
-            si -= ar * bi + ai * br;
-          }
-          const double pr = xr[(o + r) * LDB + o + r], pi = xi[(o + r) * LDB + o + r];
-          const double d = pr * pr + pi * pi;
-          ur[(o + r) * LDB + o + c] = (sr * pr + si * pi) / d;
-          ui[(o + r) * LDB + o + c] = (si * pr - sr * pi) / d;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  for (int sz = 8; sz <= NB; sz *= 2) {
-    const int h = sz / 2, npair = NB / sz, per = npair * h * h;
-    // T = C A^-1 (lower) and T = A^-1 B (upper), h x h per pair
-    for (int e = tid; e < 2 * per; e += NT) {
-      const int up = e >= per, rest = e - up * per;
-      const int pr_ = rest / (h * h), r = (rest / h) % h, c = rest % h;
-      const int o = pr_ * sz;
-      double sr = 0.0, si = 0.0;
-      if (!up) {
-        for (int k = c; k < h; ++k) {   // C[r][k] A^-1[k][c], A^-1 lower
-          const double ar = xr[(o + h + r) * LDB + o + k], ai = xi[(o + h + r) * LDB + o + k];
-          const double br = lr[(o + k) * LDB + o + c], bi = li[(o + k) * LDB + o + c];
-          sr += ar * br - ai * bi;
-          si += ar * bi + ai * br;
-        }
-      } else {
-        for (int k = r; k < h; ++k) {   // A^-1[r][k] B[k][c], A^-1 upper
-          const double ar = ur[(o + r) * LDB + o + k], ai = ui[(o + r) * LDB + o + k];
-          const double br = xr[(o + k) * LDB + o + h + c], bi = xi[(o + k) * LDB + o + h + c];
-          sr += ar * br - ai * bi;
-          si += ar * bi + ai * br;
-        }
-      }
-      tr[e] = sr;
-      ti[e] = si;
-    }
-    __syncthreads();
-    for (int e = tid; e < 2 * per; e += NT) {
-      const int up = e >= per, rest = e - up * per;
-      const int pr_ = rest / (h * h), r = (rest / h) % h, c = rest % h;
-      const int o = pr_ * sz;
-      const T* Tr = tr + up * per + pr_ * h * h;
-      const T* Ti = ti + up * per + pr_ * h * h;
-      double sr = 0.0, si = 0.0;
-      if (!up) {
-        for (int k = 0; k <= r; ++k) {   // -D^-1[r][k] T[k][c], D^-1 lower
-          const double ar = lr[(o + h + r) * LDB + o + h + k], ai = li[(o + h + r) * LDB + o + h + k];
-          const double br = Tr[k * h + c], bi = Ti[k * h + c];
-          sr += ar * br - ai * bi;
-          si += ar * bi + ai * br;
-        }
-        lr[(o + h + r) * LDB + o + c] = -sr;
-        li[(o + h + r) * LDB + o + c] = -si;
-      } else {
-        for (int k = 0; k <= c; ++k) {   // -T[r][k] D^-1[k][c], D^-1 upper
-          const double ar = Tr[r * h + k], ai = Ti[r * h + k];
-          const double br = ur[(o + h + k) * LDB + o + h + c], bi = ui[(o + h + k) * LDB + o + h + c];
-          sr += ar * br - ai * bi;
-          si += ar * bi + ai * br;
-        }
-        ur[(o + r) * LDB + o + h + c] = -sr;
-        ui[(o + r) * LDB + o + h + c] = -si;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-}  // namespace
-
 template <typename T, int WAVES, int RT, int CT>
 __global__ void __launch_bounds__(WAVES * 64)
 lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           int N, int Np, int L, T* __restrict__ F,
           int* __restrict__ perm_out, T* __restrict__ tri,
-          double* __restrict__ lad, double* __restrict__ growth) {
+          double* __restrict__ lad, double* __restrict__ growth,
+          const int* __restrict__ only, int want) {
   typedef Mma<T> M;
   typedef typename M::v4 V4;
   constexpr int NB = 16 * CT;
@@ -224,6 +74,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   constexpr int KPL = NB / 4;   // k values per lane group per panel
   extern __shared__ double lds_raw[];
   const int b = blockIdx.x;
+  if (only && only[b] != want) return;   // matrix not selected
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int g = lane >> 4, q = lane & 15;
   const int ntiles = Np >> 4;
@@ -637,7 +488,8 @@ size_t trtri_lds_bytes(int Np, int NB) {
 template <typename T, int WAVES, int RT, int CT>
 __global__ void __launch_bounds__(WAVES * 64)
 trtri_kernel(int Np, T* __restrict__ F, const int* __restrict__ perm_g,
-             const T* __restrict__ tri) {
+             const T* __restrict__ tri, const int* __restrict__ only,
+             int want) {
   typedef Mma<T> M;
   typedef typename M::v4 V4;
   constexpr int NB = 16 * CT;
@@ -645,6 +497,7 @@ trtri_kernel(int Np, T* __restrict__ F, const int* __restrict__ perm_g,
   constexpr int KPL = NB / 4;
   extern __shared__ double lds_raw[];
   const int b = blockIdx.x;
+  if (only && only[b] != want) return;   // matrix not selected
   const int upper = (blockIdx.y == 0);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int g = lane >> 4, q = lane & 15;
@@ -796,9 +649,11 @@ constexpr int kDDParts = 8;   // 256 threads = 32 positions x 8 s-slices
 template <typename T>
 __global__ void __launch_bounds__(256)
 diagdot_kernel(int N, int Np, const T* __restrict__ F,
-               const int* __restrict__ perm_g, double* __restrict__ dg) {
+               const int* __restrict__ perm_g, double* __restrict__ dg,
+               const int* __restrict__ only, int want) {
   const int j0 = blockIdx.x * kDD;
   const int b = blockIdx.y;
+  if (only && only[b] != want) return;   // matrix not selected
   const int tid = threadIdx.x;
   __shared__ double wr[kDD][kDD + 1], wi[kDD][kDD + 1];   // [j][s]
   __shared__ double vr[kDD][kDD + 1], vi[kDD][kDD + 1];   // [s][j]
@@ -881,37 +736,44 @@ namespace {
 template <typename T, int WAVES, int RT, int CT>
 hipError_t run_lu(const MatDesc* descs, const double* hbuf, int B, int N,
                   int Np, int L, T* F, int* perm, T* tri, double* lad,
-                  double* growth, hipStream_t st) {
+                  double* growth, hipStream_t st, const int* only = nullptr,
+                  int want = 0) {
   const size_t lds = lu_lds_bytes<T>(Np, 16 * CT, WAVES);
   auto kern = lu_kernel<T, WAVES, RT, CT>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-  mark_begin(K_LU, st);
+  const int cls = only ? K_FALLBACK : K_LU;
+  mark_begin(cls, st);
   hipLaunchKernelGGL(kern, dim3(B), dim3(WAVES * 64), lds, st, descs, hbuf, N,
-                     Np, L, F, perm, tri, lad, growth);
-  mark_end(K_LU, st);
+                     Np, L, F, perm, tri, lad, growth, only, want);
+  mark_end(cls, st);
   return hipGetLastError();
 }
 
+// both: W = U^-1 and V = L^-1 (grid y = 2); otherwise only W.
 template <typename T, int WAVES, int RT, int CT>
 hipError_t run_trtri(int B, int Np, T* F, const int* perm, const T* tri,
-                     hipStream_t st) {
+                     hipStream_t st, bool both = true,
+                     const int* only = nullptr, int want = 0) {
   const size_t lds = trtri_lds_bytes<T>(Np, 16 * CT);
-  mark_begin(K_TRTRI, st);
-  hipLaunchKernelGGL((trtri_kernel<T, WAVES, RT, CT>), dim3(B, 2),
-                     dim3(WAVES * 64), lds, st, Np, F, perm, tri);
-  mark_end(K_TRTRI, st);
+  const int cls = !both ? K_TRTRI_SYM : only ? K_FALLBACK : K_TRTRI;
+  mark_begin(cls, st);
+  hipLaunchKernelGGL((trtri_kernel<T, WAVES, RT, CT>), dim3(B, both ? 2 : 1),
+                     dim3(WAVES * 64), lds, st, Np, F, perm, tri, only, want);
+  mark_end(cls, st);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t run_diagdot(int B, int N, int Np, const T* F, const int* perm,
-                       double* dg, hipStream_t st) {
-  mark_begin(K_DIAGDOT, st);
+                       double* dg, hipStream_t st, const int* only = nullptr,
+                       int want = 0) {
+  const int cls = only ? K_FALLBACK : K_DIAGDOT;
+  mark_begin(cls, st);
   hipLaunchKernelGGL(diagdot_kernel<T>, dim3((Np + kDD - 1) / kDD, B),
-                     dim3(256), 0, st, N, Np, F, perm, dg);
-  mark_end(K_DIAGDOT, st);
+                     dim3(256), 0, st, N, Np, F, perm, dg, only, want);
+  mark_end(cls, st);
   return hipGetLastError();
 }
 
@@ -947,27 +809,38 @@ BlockedPlan blocked_plan_f64(int N) { return blocked_plan(N, false); }
 hipError_t blocked_lu_f64(const BlockedPlan& p, const MatDesc* descs,
                           const double* hbuf, int B, int N, int L, double* F,
                           int* perm, double* tri, double* lad, double* growth,
-                          hipStream_t st) {
+                          hipStream_t st, const int* only, int want) {
   switch (p.cfg) {
-    case 0: return run_lu<double, 4, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
-    case 1: return run_lu<double, 8, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
-    case 2: return run_lu<double, 16, 4, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 0: return run_lu<double, 4, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st, only, want);
+    case 1: return run_lu<double, 8, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st, only, want);
+    case 2: return run_lu<double, 16, 4, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st, only, want);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t blocked_inv_f64(const BlockedPlan& p, int B, int N, double* F,
                            const int* perm, const double* tri, double* dg,
-                           hipStream_t st) {
+                           hipStream_t st, const int* only, int want) {
   hipError_t e;
   switch (p.cfg) {
-    case 0: e = run_trtri<double, 4, 4, 2>(B, p.Np, F, perm, tri, st); break;
-    case 1: e = run_trtri<double, 8, 4, 2>(B, p.Np, F, perm, tri, st); break;
-    case 2: e = run_trtri<double, 8, 8, 1>(B, p.Np, F, perm, tri, st); break;
+    case 0: e = run_trtri<double, 4, 4, 2>(B, p.Np, F, perm, tri, st, true, only, want); break;
+    case 1: e = run_trtri<double, 8, 4, 2>(B, p.Np, F, perm, tri, st, true, only, want); break;
+    case 2: e = run_trtri<double, 8, 8, 1>(B, p.Np, F, perm, tri, st, true, only, want); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  return run_diagdot<double>(B, N, p.Np, F, perm, dg, st);
+  return run_diagdot<double>(B, N, p.Np, F, perm, dg, st, only, want);
+}
+
+hipError_t blocked_trtri_upper_f64(const BlockedPlan& p, int B, double* F,
+                                   const int* perm, const double* tri,
+                                   hipStream_t st, const int* only, int want) {
+  switch (p.cfg) {
+    case 0: return run_trtri<double, 4, 4, 2>(B, p.Np, F, perm, tri, st, false, only, want);
+    case 1: return run_trtri<double, 8, 4, 2>(B, p.Np, F, perm, tri, st, false, only, want);
+    case 2: return run_trtri<double, 8, 8, 1>(B, p.Np, F, perm, tri, st, false, only, want);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t blocked_lu_f32(const BlockedPlan& p, const MatDesc* descs,

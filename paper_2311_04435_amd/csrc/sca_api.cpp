@@ -62,7 +62,8 @@ sca_status validate_params(const sca_params* p) {
     return fail(SCA_EINVAL, "n_max=%d: must be in [1, %d]", p->n_max, kMaxNmax);
   if (p->precision != SCA_FP64 && p->precision != SCA_FP32_REFINED)
     return fail(SCA_EINVAL, "precision=%d: unknown", p->precision);
-  if (p->reserved != 0) return fail(SCA_EINVAL, "reserved field must be 0");
+  if (p->factor != SCA_FACTOR_LU && p->factor != SCA_FACTOR_LDLT)
+    return fail(SCA_EINVAL, "factor=%d: unknown", p->factor);
   if (!std::isfinite(p->t) || !std::isfinite(p->delta))
     return fail(SCA_EINVAL, "t and delta must be finite");
   if (!(p->U > 0.0) || !std::isfinite(p->U))
@@ -70,10 +71,15 @@ sca_status validate_params(const sca_params* p) {
   if (!(p->T > 0.0) || !std::isfinite(p->T))
     return fail(SCA_EINVAL, "T=%g: must be finite and > 0", p->T);
   const int N = p->L * p->L;
-  if (!path_supported(N, p->precision))
-    return fail(SCA_EUNSUPPORTED, "N=%d with precision %d is not built", N,
-                p->precision);
+  if (!path_supported(N, route_of(p)))
+    return fail(SCA_EUNSUPPORTED, "N=%d with precision %d and factor %d is "
+                "not built", N, p->precision, p->factor);
   return SCA_OK;
+}
+
+int route_of(const sca_params* p) {
+  return (p->precision == SCA_FP32_REFINED ? kModeFp32 : 0) |
+         (p->factor == SCA_FACTOR_LDLT ? kModeSym : 0);
 }
 
 sca_status check_device_ptr(int device, const void* ptr, const char* name,
@@ -287,27 +293,27 @@ sca_status begin_call(sca_ctx* ctx, const sca_params* p) {
 // corrects an error of FP32 size.
 constexpr double kFp32GrowthMax = 1e3;
 
-bool growth_exceeded(int precision, double growth) {
-  return precision == SCA_FP32_REFINED && !(growth <= kFp32GrowthMax);
+bool growth_exceeded(int mode, double growth) {
+  return (mode & kModeFp32) && !(growth <= kFp32GrowthMax);
 }
 
 sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
                        double* grad, double* omega2, ProbStats* st_out) {
   const int N = p->L * p->L, M = p->n_max, B = 2 * M;
-  Carve c0 = carve(nullptr, 1, N, B, p->precision, true, true,
-                   factor_workspace_bytes(N, B, p->precision));
+  Carve c0 = carve(nullptr, 1, N, B, route_of(p), true, true,
+                   factor_workspace_bytes(N, B, route_of(p)));
   sca_status s = ensure_ws(ctx, c0.total);
   if (s) return s;
-  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, true, true,
-                  factor_workspace_bytes(N, B, p->precision));
+  Carve c = carve((char*)ctx->ws, 1, N, B, route_of(p), true, true,
+                  factor_workspace_bytes(N, B, route_of(p)));
   ProbDesc P = make_prob(p, phi, grad);
-  s = run_batch(ctx, c, &P, 1, p->L, B, B, p->precision, false, true);
+  s = run_batch(ctx, c, &P, 1, p->L, B, B, route_of(p), false, true);
   if (s) return s;
   ProbStats S;
   s = read_stats(ctx, c, 1, &S);
   if (s) return s;
-  if (growth_exceeded(p->precision, S.pivot_growth) && !S.nonfinite) {
-    if (!path_supported(N, SCA_FP64))
+  if (growth_exceeded(route_of(p), S.pivot_growth) && !S.nonfinite) {
+    if (!path_supported(N, route_of(p) & ~kModeFp32))
       return fail(SCA_ENUMERIC, "FP32 pivot growth %.3g above %.0e and no "
                   "FP64 path for N=%d", S.pivot_growth, kFp32GrowthMax, N);
     sca_params q = *p;
@@ -371,7 +377,7 @@ size_t sca_footprint_bytes(const sca_params* p) {
   std::string saved = g_err;
   if (validate_params(p) != SCA_OK) return 0;
   g_err = saved;
-  return footprint(p->L * p->L, p->n_max, p->precision);
+  return footprint(p->L * p->L, p->n_max, route_of(p));
 }
 
 sca_status sca_potential(sca_ctx* ctx, const sca_params* p, const double* phi,
@@ -409,7 +415,7 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
   if ((s = check_dev_ptr(ctx, v, "v"))) return s;
 
   const int N = p->L * p->L, M = p->n_max, B = 2 * M;
-  int prec = p->precision;
+  int prec = route_of(p);
   Carve c;
   auto setup = [&]() -> sca_status {
     const size_t fb = factor_workspace_bytes(N, B, prec);
@@ -444,8 +450,8 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
       if (growth_exceeded(prec, S.pivot_growth)) {
         // the remaining steps run in FP64 where that path is built
         res->flags |= SCA_FLAG_PIVOT_GROWTH;
-        if (path_supported(N, SCA_FP64)) {
-          prec = SCA_FP64;
+        if (path_supported(N, prec & ~kModeFp32)) {
+          prec &= ~kModeFp32;
           if ((s = setup())) return s;
           P.adam_t = o->t0 + done;
           P.steps_left = o->n_steps - done;
@@ -497,10 +503,10 @@ sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
   if ((s = check_dev_ptr(ctx, logabsdet, "logabsdet"))) return s;
   if ((s = check_dev_ptr(ctx, diag, "diag"))) return s;
   const int N = p->L * p->L, B = 2 * n_z;
-  const size_t fb = factor_workspace_bytes(N, B, p->precision);
-  Carve c0 = carve(nullptr, 1, N, B, p->precision, false, false, fb);
+  const size_t fb = factor_workspace_bytes(N, B, route_of(p));
+  Carve c0 = carve(nullptr, 1, N, B, route_of(p), false, false, fb);
   if ((s = ensure_ws(ctx, c0.total))) return s;
-  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, false, false, fb);
+  Carve c = carve((char*)ctx->ws, 1, N, B, route_of(p), false, false, fb);
   ProbDesc P = make_prob(p, phi, nullptr);
   hipStream_t st = ctx->stream;
   if ((s = ensure_pinned(ctx, sizeof P))) return s;
@@ -509,7 +515,7 @@ sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
   HIP_TRY(launch_shift_descs(z, n_z, p->t, 0, N, c.descs, st));
-  HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, p->L, p->precision, logabsdet,
+  HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, p->L, route_of(p), logabsdet,
                        diag, c.growth, c.fact, st));
   HIP_TRY(hipStreamSynchronize(st));
   return SCA_OK;
@@ -528,12 +534,12 @@ sca_status sca_dos(sca_ctx* ctx, const sca_params* p, const double* phi,
   if ((s = check_dev_ptr(ctx, w, "w"))) return s;
   if ((s = check_dev_ptr(ctx, rho, "rho"))) return s;
   const int N = p->L * p->L, B = 2 * n_w;
-  const size_t fb = factor_workspace_bytes(N, B, p->precision);
+  const size_t fb = factor_workspace_bytes(N, B, route_of(p));
   // shifts z_j = w_j + i eta live after the carve
-  Carve c0 = carve(nullptr, 1, N, B, p->precision, true, true, fb);
+  Carve c0 = carve(nullptr, 1, N, B, route_of(p), true, true, fb);
   const size_t zoff = c0.total;
   if ((s = ensure_ws(ctx, zoff + align256(sizeof(double) * 2 * n_w)))) return s;
-  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, true, true, fb);
+  Carve c = carve((char*)ctx->ws, 1, N, B, route_of(p), true, true, fb);
   double* zbuf = (double*)((char*)ctx->ws + zoff);
   ProbDesc P = make_prob(p, phi, nullptr);
   hipStream_t st = ctx->stream;
@@ -544,7 +550,7 @@ sca_status sca_dos(sca_ctx* ctx, const sca_params* p, const double* phi,
   HIP_TRY(launch_make_shifts(w, n_w, eta, zbuf, st));
   HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
   HIP_TRY(launch_shift_descs(zbuf, n_w, p->t, 0, N, c.descs, st));
-  HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, p->L, p->precision, c.lad, c.dg,
+  HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, p->L, route_of(p), c.lad, c.dg,
                        c.growth, c.fact, st));
   HIP_TRY(launch_dos_reduce(c.dg, n_w, N, rho, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -556,7 +562,7 @@ size_t sca_factor_bytes(const sca_params* p) {
   if (validate_params(p) != SCA_OK) return 0;
   g_err = saved;
   const int N = p->L * p->L, B = 2 * p->n_max;
-  return autograd_factor_bytes(N, B, p->precision);
+  return autograd_factor_bytes(N, B, route_of(p));
 }
 
 sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
@@ -568,10 +574,10 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
   if ((s = check_dev_ptr(ctx, omega2, "omega2"))) return s;
   const int N = p->L * p->L, M = p->n_max, B = 2 * M;
-  Carve c0 = carve(nullptr, 1, N, B, p->precision, false, false, 0);
+  Carve c0 = carve(nullptr, 1, N, B, route_of(p), false, false, 0);
   if ((s = ensure_ws(ctx, c0.total))) return s;
-  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, false, false, 0);
-  AutogradLayout lay = autograd_layout(factors, N, B, p->precision);
+  Carve c = carve((char*)ctx->ws, 1, N, B, route_of(p), false, false, 0);
+  AutogradLayout lay = autograd_layout(factors, N, B, route_of(p));
   c.lad = lay.lad;
   c.dg = lay.dg;
   c.fact = lay.fact;
@@ -582,11 +588,11 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
   std::memcpy(ctx->pinned, &P, sizeof P);
   FactorHeader* hh = reinterpret_cast<FactorHeader*>(
       static_cast<char*>(ctx->pinned) + 256);
-  *hh = FactorHeader{kFactorsReady, p->L, p->n_max, p->precision};
+  *hh = FactorHeader{kFactorsReady, p->L, p->n_max, route_of(p)};
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_matsubara_descs(c.probs, 1, B, c.descs, st));
   HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
-  HIP_TRY(factor_forward(c.descs, c.hbuf, B, N, p->L, p->precision, c.lad,
+  HIP_TRY(factor_forward(c.descs, c.hbuf, B, N, p->L, route_of(p), c.lad,
                          c.dg, c.growth, c.fact, st));
   HIP_TRY(launch_reduce_omega(c.probs, 1, N, c.lad, c.growth, c.stats, c.rws, st));
   HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice, st));
@@ -610,10 +616,10 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
   if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
   const int N = p->L * p->L, M = p->n_max, B = 2 * M;
-  Carve c0 = carve(nullptr, 1, N, B, p->precision, false, false, 0);
+  Carve c0 = carve(nullptr, 1, N, B, route_of(p), false, false, 0);
   if ((s = ensure_ws(ctx, c0.total))) return s;
-  Carve c = carve((char*)ctx->ws, 1, N, B, p->precision, false, false, 0);
-  AutogradLayout lay = autograd_layout(factors, N, B, p->precision);
+  Carve c = carve((char*)ctx->ws, 1, N, B, route_of(p), false, false, 0);
+  AutogradLayout lay = autograd_layout(factors, N, B, route_of(p));
   ProbDesc P = make_prob(p, phi, grad);
   hipStream_t st = ctx->stream;
   if ((s = ensure_pinned(ctx, 512))) return s;
@@ -627,15 +633,15 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
                 "sca_grad_from_factors (this path inverts them in place); "
                 "call sca_factorize again");
   if (hh->state != kFactorsReady || hh->L != p->L || hh->n_max != p->n_max ||
-      hh->precision != p->precision)
+      hh->mode != route_of(p))
     return fail(SCA_EINVAL, "factors do not hold a factorisation of these "
                 "params (sca_factorize not called with them)");
   std::memcpy(ctx->pinned, &P, sizeof P);
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
-  HIP_TRY(factor_backward(B, N, p->precision, lay.lad, lay.dg, lay.fact, st));
+  HIP_TRY(factor_backward(B, N, route_of(p), lay.lad, lay.dg, lay.fact, st));
   HIP_TRY(launch_reduce(c.probs, 1, N, lay.lad, lay.dg, lay.growth, c.stats,
                         false, c.rws, st));
-  if (factor_backward_consumes(N, p->precision)) {
+  if (factor_backward_consumes(N, route_of(p))) {
     hh->state = kFactorsConsumed;
     HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice,
                            st));

@@ -1,7 +1,11 @@
-// Factorisation path selection.
-//   N <= 64  : fused small kernel (matrix in LDS), FP64 for both precisions
-//              (these matrices are too small for the FP32 route to pay).
+// Factorisation path selection.  `mode` is the route code of
+// sca_runtime.h: bit 0 FP32 refined, bit 1 symmetric (unpivoted L D L^T).
+//   N <= 64  : fused small kernel (matrix in LDS), FP64 pivoted LU for every
+//              mode (these matrices are too small for the other routes to
+//              pay).
 //   FP64, N <= 1024: blocked LU, then U^-1 / L^-1, then the diagonal.
+//   FP64 symmetric, N <= 1024: blocked L D L^T, L^-T, the diagonal; the
+//              matrices whose growth check fails are redone by the LU.
 //   FP32 refined, N <= 2304: blocked complex64 LU and U^-1 / L^-1, the
 //              product X = W V, then the FP64 Newton diagonal and the
 //              refined log-determinant.
@@ -15,12 +19,15 @@ namespace sca {
 namespace {
 constexpr int kSmallMax = 64;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+bool fp32_mode(int mode) { return (mode & kModeFp32) != 0; }
+bool sym_mode(int mode) { return (mode & kModeSym) != 0; }
 }  // namespace
 
-bool path_supported(int N, int precision) {
-  if (N < 1) return false;
+bool path_supported(int N, int mode) {
+  if (N < 1 || mode < 0 || mode > 3) return false;
   if (N <= kSmallMax) return true;
-  return blocked_plan(N, precision != 0).cfg >= 0;
+  if (fp32_mode(mode) && sym_mode(mode)) return false;
+  return blocked_plan(N, fp32_mode(mode)).cfg >= 0;
 }
 
 namespace {
@@ -30,23 +37,30 @@ size_t refine_extra_bytes(const BlockedPlan& p, int B) {
        + align256(sizeof(double) * (size_t)B * refine_blocks(p.Np));  // parts
 }
 
+size_t sym_extra_bytes(const BlockedPlan& p, int B) {
+  return align256(sizeof(double) * 2 * (size_t)B * p.Np)   // 1/d
+       + align256(sizeof(int) * (size_t)B);                // fallback flags
+}
+
 }  // namespace
 
-size_t factor_workspace_bytes(int N, int B, int precision) {
+size_t factor_workspace_bytes(int N, int B, int mode) {
   if (N <= kSmallMax) return 0;
-  const BlockedPlan p = blocked_plan(N, precision != 0);
+  const BlockedPlan p = blocked_plan(N, fp32_mode(mode));
   if (p.cfg < 0) return 0;
-  if (precision == 0) return blocked_factor_bytes(p, B, sizeof(double));
-  return blocked_factor_bytes(p, B, sizeof(float)) + refine_extra_bytes(p, B);
+  if (fp32_mode(mode))
+    return blocked_factor_bytes(p, B, sizeof(float)) + refine_extra_bytes(p, B);
+  size_t bytes = blocked_factor_bytes(p, B, sizeof(double));
+  if (sym_mode(mode)) bytes += sym_extra_bytes(p, B);
+  return bytes;
 }
 
 namespace {
 
 // F (planar re/im factors, B x 2 x Np x Np), perm (B x Np), tri (inverted
-// diagonal blocks); the FP32 route adds X (B x 2 x Np x Np) and the
-// per-block log-det parts.
+// diagonal blocks), then the route's extra buffers.
 template <typename T>
-struct BlockedBufs { T* F; int* perm; T* tri; float* X; double* parts; };
+struct BlockedBufs { T* F; int* perm; T* tri; char* extra; };
 
 template <typename T>
 BlockedBufs<T> carve_blocked(void* fact, const BlockedPlan& p, int B) {
@@ -58,9 +72,7 @@ BlockedBufs<T> carve_blocked(void* fact, const BlockedPlan& p, int B) {
   c += align256(sizeof(int) * (size_t)B * p.Np);
   r.tri = reinterpret_cast<T*>(c);
   c += align256(sizeof(T) * (size_t)B * (p.Np / p.NB) * 4 * p.NB * p.NB);
-  r.X = reinterpret_cast<float*>(c);
-  c += align256(sizeof(float) * 2 * (size_t)B * p.Np * p.Np);
-  r.parts = reinterpret_cast<double*>(c);
+  r.extra = c;
   return r;
 }
 
@@ -69,28 +81,57 @@ hipError_t fp32r_batch(const BlockedPlan& p, const MatDesc* descs,
                        double* dg, double* growth, void* fact,
                        hipStream_t st) {
   BlockedBufs<float> bb = carve_blocked<float>(fact, p, B);
+  float* X = reinterpret_cast<float*>(bb.extra);
+  double* parts = reinterpret_cast<double*>(
+      bb.extra + align256(sizeof(float) * 2 * (size_t)B * p.Np * p.Np));
   hipError_t e = blocked_lu_f32(p, descs, hbuf, B, N, L, bb.F, bb.perm,
                                 bb.tri, lad, growth, st);
   if (e == hipSuccess) e = blocked_trtri_f32(p, B, bb.F, bb.perm, bb.tri, st);
-  if (e == hipSuccess) e = launch_wv_gemm(B, p.Np, bb.F, bb.perm, bb.X, st);
+  if (e == hipSuccess) e = launch_wv_gemm(B, p.Np, bb.F, bb.perm, X, st);
   if (e == hipSuccess)
-    e = launch_refine(B, N, p.Np, L, descs, hbuf, bb.F, bb.perm, bb.X, dg,
-                      bb.parts, lad, st);
+    e = launch_refine(B, N, p.Np, L, descs, hbuf, bb.F, bb.perm, X, dg,
+                      parts, lad, st);
+  return e;
+}
+
+// Symmetric route; the matrices the L D L^T kernel flags are redone by the
+// pivoted LU (predicated launches that skip every other matrix).
+hipError_t sym_batch(const BlockedPlan& p, const MatDesc* descs,
+                     const double* hbuf, int B, int N, int L, double* lad,
+                     double* dg, double* growth, void* fact, hipStream_t st) {
+  BlockedBufs<double> bb = carve_blocked<double>(fact, p, B);
+  double* invd = reinterpret_cast<double*>(bb.extra);
+  int* flags = reinterpret_cast<int*>(
+      bb.extra + align256(sizeof(double) * 2 * (size_t)B * p.Np));
+  hipError_t e = blocked_ldlt_f64(p, descs, hbuf, B, N, L, bb.F, bb.perm,
+                                  bb.tri, invd, lad, growth, flags, st);
+  if (e == hipSuccess)
+    e = blocked_trtri_upper_f64(p, B, bb.F, bb.perm, bb.tri, st, flags, 0);
+  if (e == hipSuccess)
+    e = launch_symdiag_f64(B, N, p.Np, bb.F, invd, dg, st, flags, 0);
+  if (e == hipSuccess)
+    e = blocked_lu_f64(p, descs, hbuf, B, N, L, bb.F, bb.perm, bb.tri, lad,
+                       growth, st, flags, 1);
+  if (e == hipSuccess)
+    e = blocked_inv_f64(p, B, N, bb.F, bb.perm, bb.tri, dg, st, flags, 1);
   return e;
 }
 
 }  // namespace
 
 hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
-                        int L, int precision, double* lad, double* dg,
+                        int L, int mode, double* lad, double* dg,
                         double* growth, void* fact, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   if (N <= kSmallMax)
     return launch_small_factor(descs, hbuf, B, N, L, lad, dg, growth, st);
-  const BlockedPlan p = blocked_plan(N, precision != 0);
-  if (p.cfg < 0) return hipErrorInvalidValue;
-  if (precision != 0)
+  const BlockedPlan p = blocked_plan(N, fp32_mode(mode));
+  if (p.cfg < 0 || (fp32_mode(mode) && sym_mode(mode)))
+    return hipErrorInvalidValue;
+  if (fp32_mode(mode))
     return fp32r_batch(p, descs, hbuf, B, N, L, lad, dg, growth, fact, st);
+  if (sym_mode(mode))
+    return sym_batch(p, descs, hbuf, B, N, L, lad, dg, growth, fact, st);
   BlockedBufs<double> bb = carve_blocked<double>(fact, p, B);
   hipError_t e = blocked_lu_f64(p, descs, hbuf, B, N, L, bb.F, bb.perm, bb.tri,
                                 lad, growth, st);
@@ -98,21 +139,20 @@ hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
   return blocked_inv_f64(p, B, N, bb.F, bb.perm, bb.tri, dg, st);
 }
 
-bool factor_backward_consumes(int N, int precision) {
-  return N > kSmallMax && precision == 0;
+bool factor_backward_consumes(int N, int mode) {
+  return N > kSmallMax && mode == 0;
 }
 
-size_t autograd_factor_bytes(int N, int B, int precision) {
+size_t autograd_factor_bytes(int N, int B, int mode) {
   size_t bytes = align256(sizeof(FactorHeader))
                + align256(sizeof(double) * (size_t)B)        // lad
                + align256(sizeof(double) * (size_t)B)        // growth
                + align256(sizeof(double) * 2 * (size_t)B * N)  // dg
-               + factor_workspace_bytes(N, B, precision);   // LU factors
+               + factor_workspace_bytes(N, B, mode);   // factors
   return bytes;
 }
 
-AutogradLayout autograd_layout(void* base, int N, int B, int precision) {
-  (void)precision;
+AutogradLayout autograd_layout(void* base, int N, int B, int mode) {
   char* p = static_cast<char*>(base);
   AutogradLayout a;
   a.head = reinterpret_cast<FactorHeader*>(p);
@@ -123,19 +163,18 @@ AutogradLayout autograd_layout(void* base, int N, int B, int precision) {
   p += align256(sizeof(double) * (size_t)B);
   a.dg = reinterpret_cast<double*>(p);
   p += align256(sizeof(double) * 2 * (size_t)B * N);
-  a.fact = factor_workspace_bytes(N, B, precision) ? p : nullptr;
+  a.fact = factor_workspace_bytes(N, B, mode) ? p : nullptr;
   return a;
 }
 
 hipError_t factor_forward(const MatDesc* descs, const double* hbuf, int B,
-                          int N, int L, int precision, double* lad, double* dg,
+                          int N, int L, int mode, double* lad, double* dg,
                           double* growth, void* fact, hipStream_t st) {
-  // the small path forms diag(A^-1) in the same pass as the LU; the FP32
-  // route needs W and V for the refined log-determinant, so it completes
-  // the diagonal in the forward as well
-  if (N <= kSmallMax || precision != 0)
-    return factor_batch(descs, hbuf, B, N, L, precision, lad, dg, growth, fact,
-                        st);
+  // only the FP64 pivoted route splits: the small path forms diag(A^-1) in
+  // the same pass as the LU, the FP32 route needs W and V for the refined
+  // log-determinant, the symmetric route's fallback needs both halves
+  if (!factor_backward_consumes(N, mode))
+    return factor_batch(descs, hbuf, B, N, L, mode, lad, dg, growth, fact, st);
   const BlockedPlan p = blocked_plan_f64(N);
   if (p.cfg < 0) return hipErrorInvalidValue;
   BlockedBufs<double> bb = carve_blocked<double>(fact, p, B);
@@ -143,10 +182,10 @@ hipError_t factor_forward(const MatDesc* descs, const double* hbuf, int B,
                         growth, st);
 }
 
-hipError_t factor_backward(int B, int N, int precision, const double* lad,
+hipError_t factor_backward(int B, int N, int mode, const double* lad,
                            double* dg, void* fact, hipStream_t st) {
   (void)lad;
-  if (N <= kSmallMax || precision != 0) return hipSuccess;   // dg complete
+  if (!factor_backward_consumes(N, mode)) return hipSuccess;   // dg complete
   const BlockedPlan p = blocked_plan_f64(N);
   if (p.cfg < 0) return hipErrorInvalidValue;
   BlockedBufs<double> bb = carve_blocked<double>(fact, p, B);

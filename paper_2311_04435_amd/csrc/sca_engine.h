@@ -22,6 +22,8 @@ sca_status fail(sca_status s, const char* fmt, ...);
   } while (0)
 
 sca_status validate_params(const sca_params* p);
+// Route code (kModeFp32 | kModeSym bits) of a parameter point.
+int route_of(const sca_params* p);
 sca_status validate_adam_opts(const sca_adam_opts* o);
 // ptr must be device (or managed) memory of `device`; NULL only if allowed.
 sca_status check_device_ptr(int device, const void* ptr, const char* name,

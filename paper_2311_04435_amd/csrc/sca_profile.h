@@ -16,7 +16,11 @@ enum KernelClass {
   K_SETUP = 5,    // descriptors and diagonal vectors
   K_REFINE = 6,   // FP64 refinement of the FP32 route
   K_WVGEMM = 7,   // X = U^-1 L^-1 of the FP32 route
-  K_COUNT = 8
+  K_LDLT = 8,     // symmetric route: L D L^T
+  K_TRTRI_SYM = 9,  // symmetric route: L^-T
+  K_SYMDIAG = 10,   // symmetric route: diagonal of A^-1
+  K_FALLBACK = 11,  // symmetric route: pivoted LU of flagged matrices
+  K_COUNT = 16
 };
 
 struct Profiler {

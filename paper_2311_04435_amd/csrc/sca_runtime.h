@@ -1,5 +1,6 @@
 // Dispatch layer between the C ABI and the kernels: picks the factorisation
-// path from N and the precision and sizes its scratch memory.
+// path from N and the route (precision and factorisation) and sizes its
+// scratch memory.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -11,18 +12,23 @@ constexpr int kMaxL = 64;           // N <= 4096 sites
 constexpr int kMaxNmax = 1 << 16;   // Matsubara frequencies per spin
 constexpr int kMaxShifts = 1 << 20; // shifts per sca_dos / sca_shifted_terms
 
-// Whether a factorisation path exists for N sites at `precision`.
-bool path_supported(int N, int precision);
+// Route code of a parameter point (the `mode` argument of the functions
+// below): bit 0 = FP32 refined, bit 1 = symmetric L D L^T.
+constexpr int kModeFp32 = 1;
+constexpr int kModeSym = 2;
+
+// Whether a factorisation path exists for N sites on route `mode`.
+bool path_supported(int N, int mode);
 
 // Scratch (bytes) the factorisation of B matrices of N sites needs beyond
 // the per-matrix outputs (0 for the fused small path).
-size_t factor_workspace_bytes(int N, int B, int precision);
+size_t factor_workspace_bytes(int N, int B, int mode);
 
 // ln|det A_b| -> lad[b], diag(A_b^-1) -> dg[b][N][2] (re, im), pivot growth
 // -> growth[b], for the B matrices described by descs.  `fact` is the
-// scratch of factor_workspace_bytes(N, B, precision) bytes.
+// scratch of factor_workspace_bytes(N, B, mode) bytes.
 hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
-                        int L, int precision, double* lad, double* dg,
+                        int L, int mode, double* lad, double* dg,
                         double* growth, void* fact, hipStream_t st);
 
 // Autograd split of factor_batch.  The forward writes lad and growth and
@@ -30,20 +36,20 @@ hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
 // what the backward needs; the backward completes dg from it.  The buffer
 // starts with a header naming the problem shape and whether the factors are
 // still usable: the FP64 blocked backward inverts them in place.
-struct FactorHeader { uint32_t state; int32_t L, n_max, precision; };
+struct FactorHeader { uint32_t state; int32_t L, n_max, mode; };
 constexpr uint32_t kFactorsReady = 0x5CA10001u;
 constexpr uint32_t kFactorsConsumed = 0x5CA10002u;
 struct AutogradLayout {
   FactorHeader* head; double* lad; double* growth; double* dg; void* fact;
 };
 // Whether factor_backward overwrites the factors it reads.
-bool factor_backward_consumes(int N, int precision);
-size_t autograd_factor_bytes(int N, int B, int precision);
-AutogradLayout autograd_layout(void* base, int N, int B, int precision);
+bool factor_backward_consumes(int N, int mode);
+size_t autograd_factor_bytes(int N, int B, int mode);
+AutogradLayout autograd_layout(void* base, int N, int B, int mode);
 hipError_t factor_forward(const MatDesc* descs, const double* hbuf, int B,
-                          int N, int L, int precision, double* lad, double* dg,
+                          int N, int L, int mode, double* lad, double* dg,
                           double* growth, void* fact, hipStream_t st);
-hipError_t factor_backward(int B, int N, int precision, const double* lad,
+hipError_t factor_backward(int B, int N, int mode, const double* lad,
                            double* dg, void* fact, hipStream_t st);
 
 // Omega, Omega~ of every problem without the gradient (dg not read).
@@ -55,6 +61,6 @@ hipError_t launch_reduce_omega(ProbDesc* probs, int nprob, int N,
 hipError_t launch_make_shifts(const double* w, int n_w, double eta, double* z,
                               hipStream_t st);
 
-size_t footprint(int N, int M, int precision);
+size_t footprint(int N, int M, int mode);
 
 }  // namespace sca

@@ -71,7 +71,7 @@ struct Request {
 };
 
 struct Group {
-  int L = 0, M = 0, precision = 0, N = 0, cap = 0;
+  int L = 0, M = 0, precision = 0, N = 0, cap = 0;   // precision: route code
   hipStream_t st = nullptr;
   hipEvent_t ev = nullptr;
   void* ws = nullptr;
@@ -158,7 +158,7 @@ bool make_room(sca_server* s, size_t need) {
 // allows (up to max_batch); nullptr if not even one fits now.
 sca_status new_group(sca_server* s, const Request* r, Group** out) {
   *out = nullptr;
-  const int N = r->p.L * r->p.L, M = r->p.n_max, prec = r->p.precision;
+  const int N = r->p.L * r->p.L, M = r->p.n_max, prec = route_of(&r->p);
   auto fits = [&](int cap) {
     return s->used + group_bytes(N, M, prec, cap) <= s->budget;
   };
@@ -194,7 +194,7 @@ sca_status new_group(sca_server* s, const Request* r, Group** out) {
 Group* find_group(sca_server* s, const Request* r) {
   for (auto& g : s->groups)
     if (g->L == r->p.L && g->M == r->p.n_max &&
-        g->precision == r->p.precision)
+        g->precision == route_of(&r->p))
       return g.get();
   return nullptr;
 }
@@ -281,7 +281,7 @@ void complete(sca_server* s, Group* g) {
     r->res.steps_done = r->o.n_steps;
     r->res.flags = 0;
     if (S.nonfinite) r->res.flags |= SCA_FLAG_NONFINITE;
-    if (r->p.precision == SCA_FP32_REFINED && !(S.pivot_growth <= 1e3))
+    if ((route_of(&r->p) & kModeFp32) && !(S.pivot_growth <= 1e3))
       r->res.flags |= SCA_FLAG_PIVOT_GROWTH;
     r->done = true;
     r->t_done = t;
@@ -375,7 +375,7 @@ sca_status sca_server_submit(sca_server* s, const sca_params* p,
   if ((st = check_device_ptr(s->device, phi, "phi", false))) return st;
   if ((st = check_device_ptr(s->device, m, "m", false))) return st;
   if ((st = check_device_ptr(s->device, v, "v", false))) return st;
-  const size_t one = group_bytes(p->L * p->L, p->n_max, p->precision, 1);
+  const size_t one = group_bytes(p->L * p->L, p->n_max, route_of(p), 1);
   if (one > s->budget)
     return fail(SCA_ENOMEM, "a request of L=%d needs %zu bytes, above the "
                 "server budget of %zu", p->L, one, s->budget);

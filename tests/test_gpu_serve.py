@@ -1,8 +1,8 @@
 """GPU tests of the request server (continuous batching of ADAM solves).
 
 * alone vs mix: requests of mixed shapes (fused small path, blocked FP64,
-  FP32-refined), submitted together and batched with each other, give
-  bit-for-bit the phi, moments and statistics that sca.adam_solve gives
+  FP32-refined, symmetric L D L^T), submitted together and batched with
+  each other, give bit-for-bit the phi, moments and statistics that sca.adam_solve gives
   for each alone;
 * the same under an HBM budget that holds one group at a time (requests
   wait in the queue, groups give their memory back);
@@ -33,13 +33,17 @@ def cuda(x):
 
 def mix(sca):
     out = []
-    shapes = [(4, 32, "fp64"), (8, 32, "fp64"), (4, 32, "fp64"),
-              (10, 16, "fp64"), (8, 32, "fp64"), (12, 16, "fp32r"),
-              (10, 16, "fp64"), (12, 16, "fp32r"), (4, 16, "fp64")]
-    for k, (L, M, prec) in enumerate(shapes):
+    shapes = [(4, 32, "fp64", "lu"), (8, 32, "fp64", "lu"),
+              (4, 32, "fp64", "lu"), (10, 16, "fp64", "lu"),
+              (8, 32, "fp64", "lu"), (12, 16, "fp32r", "lu"),
+              (10, 16, "fp64", "lu"), (12, 16, "fp32r", "lu"),
+              (4, 16, "fp64", "lu"), (12, 16, "fp64", "ldlt"),
+              (12, 16, "fp64", "ldlt")]
+    for k, (L, M, prec, fac) in enumerate(shapes):
         r = synth.uniform(900 + k, 4, 0.0, 1.0)
         p = sca.Params(L=L, U=2.0 + 4.0 * r[0], delta=1.5 * r[1],
-                       T=0.1 + 0.3 * r[2], n_max=M, precision=prec)
+                       T=0.1 + 0.3 * r[2], n_max=M, precision=prec,
+                       factor=fac)
         steps = 5 + int(10 * r[3])
         out.append(dict(params=p, phi0=cuda(synth.uniform(k, L * L, -0.5, 0.5)),
                         n_steps=steps, lr=0.02, final_eval=(k % 3 != 2)))
