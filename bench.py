@@ -14,7 +14,11 @@ Prints one JSON line.  Besides the contract fields it carries
                 from HIP events on the library's stream over a second,
                 profiled run of the same steps;
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample;
-  l32           steps/s of the 32x32 ionic lattice in both precisions;
+  l32           steps/s of the 32x32 ionic lattice: FP32 refined, FP64
+                pivoted LU, FP64 symmetric L D L^T;
+  symmetric_ldlt the same workload on the symmetric route (unpivoted
+                L D L^T, exact for these complex symmetric matrices, half
+                the flops) with its own roofline;
   serving       served solves/s and p50/p99 latency of a Poisson stream of
                 mixed requests through the request server, next to the
                 one-at-a-time FIFO baseline on the same GPU.
@@ -37,14 +41,18 @@ HBM_PEAK = 8000.0                       # GB/s
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled
 # by the same counters on a copy kernel of known size (read x 2.0, write x
-# 1.0); profiles/lu_f64_hubbard_20x20.md has the runs.  Keyed by (kernel
+# 1.0); profiles/lu_f64_hubbard_20x20.md and ldlt_f64_hubbard_20x20.md
+# have the runs.  Keyed by (kernel
 # class, workload, precision, factorisation) with the SHA-256 of the kernel source the
 # counters were taken on: a changed source reports null.
 TRAFFIC = {
     ("lu", "hubbard_20x20_T0.1", "fp64", "lu"): (
-        15.912e9, "c42cf787c0f4f1d6a2ba316ca8ac08268c35ecaa959c32ca766554db2774947a"),
+        15.912e9, "k_factor.hip",
+        "e726ac3eb3b7c15a071e493dad5ab794d719520546b9b75057d3dcea8d9855c8"),
+    ("ldlt", "hubbard_20x20_T0.1", "fp64", "ldlt"): (
+        8.095e9, "k_ldlt.hip",
+        "0a670676091fa10f07b4abf65fb2423ee0910818fea3802d2cefc7383488c71d"),
 }
-TRAFFIC_SRC = os.path.join(ROOT, "paper_2311_04435_amd", "csrc", "k_factor.hip")
 
 
 def measured_traffic(kernel: str, workload: str, prec: str, factor: str):
@@ -52,9 +60,10 @@ def measured_traffic(kernel: str, workload: str, prec: str, factor: str):
     hit = TRAFFIC.get((kernel, workload, prec, factor))
     if hit is None:
         return None
-    with open(TRAFFIC_SRC, "rb") as f:
+    src = os.path.join(ROOT, "paper_2311_04435_amd", "csrc", hit[1])
+    with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    return hit[0] if sha == hit[1] else None
+    return hit[0] if sha == hit[2] else None
 
 
 def kernel_work(kind: str, N: int, B: int):
@@ -152,7 +161,53 @@ def workload_rate(sca, name, prec, steps, warmup, factor="lu"):
             "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps}
 
 
-def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0):
+def route_line(sca, name, prec, factor, steps, warmup):
+    """Steps/s of a workload on a given route, with the per-kernel averages
+    (HIP events) and the roofline of its dominant kernel."""
+    out = workload_rate(sca, name, prec, steps, warmup, factor)
+    import torch
+    import synth
+    wl = synth.WORKLOADS[name]
+    p = sca.Params.from_dict(wl["params"], precision=prec, factor=factor)
+    phi = torch.as_tensor(synth.make_phi0(p.L, wl["phi0"]),
+                          dtype=torch.float64).cuda()
+    ctx = sca.Context()
+    m, v = torch.zeros_like(phi), torch.zeros_like(phi)
+    hy = wl["adam"]
+    kw = dict(lr=hy["lr"], beta1=hy["beta1"], beta2=hy["beta2"], eps=hy["eps"],
+              final_eval=False)
+    ctx.adam_solve(p, phi, m, v, warmup, **kw)
+    ctx.profile(True)
+    ctx.adam_solve(p, phi, m, v, steps, t0=warmup, **kw)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    out["kernels"] = {k: {"avg_ms": ms / n, "launches": n} for k, (ms, n) in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][0])
+    N, B = p.L * p.L, 2 * p.n_max
+    work = kernel_work(dom, N, B)
+    if work is not None:
+        amount, unit, bound = work
+        avg_s = prof[dom][0] / prof[dom][1] / 1e3
+        if unit == "flop":
+            peak = PEAK["fp32" if prec == "fp32r" else "fp64"]
+            ach = amount / avg_s / 1e12
+            out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": ach,
+                               "peak": peak, "unit": "TFLOP/s",
+                               "frac": ach / peak,
+                               "traffic": measured_traffic(dom, name, prec,
+                                                           factor)}
+        else:
+            ach = amount / avg_s / 1e9
+            out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach,
+                               "peak": HBM_PEAK, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK,
+                               "traffic": measured_traffic(dom, name, prec,
+                                                           factor)}
+    return out
+
+
+def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0,
+            factor="lu"):
     """Poisson stream of mixed requests: one at a time (FIFO, measured
     service times) vs the request server (real time)."""
     import numpy as np
@@ -162,7 +217,7 @@ def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0):
                                             latency_summary)
     reqs = []
     for r in synth.serving_stream(n_req, seed, n_max, Ls=Ls):
-        p = sca.Params.from_dict(r["params"])
+        p = sca.Params.from_dict(r["params"], factor=factor)
         phi0 = torch.as_tensor(synth.make_phi0(p.L, r["phi0"]),
                                dtype=torch.float64).cuda()
         reqs.append(dict(params=p, phi0=phi0, n_steps=steps))
@@ -196,7 +251,8 @@ def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0):
     same = all(torch.equal(results[k][0], alone[k]) for k in range(len(reqs)))
     del ctx
     return {"workload": (f"{n_req} requests, L in {sorted(set(Ls))}, "
-                         f"n_max={n_max}, {steps} ADAM steps each, FP64, "
+                         f"n_max={n_max}, {steps} ADAM steps each, FP64 "
+                         f"({'pivoted LU' if factor == 'lu' else 'L D L^T'}), "
                          f"U~U[2,8], Delta~U[0,2], T~U[0.05,0.6]"),
             "arrivals": f"Poisson, {rate:.3f}/s = {load} x FIFO capacity",
             "max_batch": max_batch,
@@ -217,12 +273,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-l32", action="store_true")
+    ap.add_argument("--no-symmetric", action="store_true",
+                    help="skip the symmetric-route line")
     ap.add_argument("--serving-requests", type=int, default=32,
                     help="0 skips the serving measurement")
     ap.add_argument("--serving-steps", type=int, default=200)
     ap.add_argument("--serving-nmax", type=int, default=256)
     ap.add_argument("--serving-L", default="8,12,16,20")
     ap.add_argument("--serving-batch", type=int, default=16)
+    ap.add_argument("--serving-factor", default="lu", help="lu | ldlt")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), "
                          "the reference for the HBM byte counters")
@@ -331,11 +390,18 @@ def main():
     }
     if not args.no_l32:
         out["l32"] = [workload_rate(sca, "ionic_32x32_U4", "fp32r", 5, 1),
-                      workload_rate(sca, "ionic_32x32_U4", "fp64", 3, 1)]
+                      workload_rate(sca, "ionic_32x32_U4", "fp64", 3, 1),
+                      workload_rate(sca, "ionic_32x32_U4", "fp64", 5, 1,
+                                    "ldlt")]
+    if args.factor == "lu" and prec == "fp64" and not args.no_symmetric:
+        # the same workload on the symmetric route (unpivoted L D L^T)
+        out["symmetric_ldlt"] = route_line(sca, args.workload, "fp64", "ldlt",
+                                           max(args.steps, 10), args.warmup)
     if args.serving_requests > 0:
         Ls = tuple(int(x) for x in args.serving_L.split(","))
         out["serving"] = serving(sca, args.serving_requests, args.serving_steps,
-                                 args.serving_nmax, Ls, args.serving_batch)
+                                 args.serving_nmax, Ls, args.serving_batch,
+                                 factor=args.serving_factor)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
