@@ -140,3 +140,25 @@ def test_fp32r_repeat_is_bitwise(sca):
     g1, o1 = sca.grad(p, phi)
     g2, o2 = sca.grad(p, phi)
     assert torch.equal(g1, g2) and torch.equal(o1, o2)
+
+
+def test_fp32r_c2_trajectory_2000_steps(sca):
+    """2000 ADAM steps on the 20x20 lattice at T = 0.1 in refined FP32
+    against the oracle's stored trajectory (tests/golden/make_c2_trajectory.py):
+    phi, |phi| and Omega~ at the end, to the refined-FP32 bar."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "c2_trajectory_20x20.json")
+    with open(path) as f:
+        gold = json.load(f)["hubbard_20x20_T0.1"]
+    wl = synth.WORKLOADS["hubbard_20x20_T0.1"]
+    p = sca.Params.from_dict(wl["params"], precision="fp32r")
+    phi, m, v, res = sca.adam_solve(p, cuda(synth.make_phi0(20, wl["phi0"])),
+                                    2000)
+    ref = np.array(gold["phi2000"])
+    e = np.max(np.abs(phi.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    e_af = abs(res["af_order"] - gold["af_order"]) / gold["af_order"]
+    e_om = abs(res["omega_tilde"] - gold["omega_tilde"]) / abs(gold["omega_tilde"])
+    print(f"fp32r 2000 steps: phi {e:.2e}  |phi| {e_af:.1e}  Omega~ {e_om:.1e}")
+    assert e < TOL and e_af < TOL and e_om < TOL
