@@ -359,3 +359,33 @@ def test_oracle_grad_matches_stored_finite_differences():
             else:
                 gd = float(g @ synth.rademacher(d["arg"], N))
             assert abs(gd - d["fd"]) <= 10 * case["floor"] + 1e-7 * abs(d["fd"])
+
+
+def test_oracle_onsite_uniform_is_a_shift():
+    """A uniform extra site potential c is the shift z -> z - c of every
+    matrix: ln|det(z - H - c)| = ln|det((z - c) - H)| (the disordered model
+    of the conclusions with zero disorder)."""
+    p = dict(L=4, t=1.0, U=4.0, delta=0.6, T=0.1, n_max=8)
+    phi = uniform(61, 16, -0.5, 0.5)
+    c = 0.37
+    z = np.array([0.3j, 1.1 + 0.2j, -0.4 + 0.05j])
+    for spin in (1, -1):
+        l1, d1 = oracle.shifted_terms(p, phi, z, spin, onsite=np.full(16, c))
+        l2, d2 = oracle.shifted_terms(p, phi, z - c, spin)
+        assert np.allclose(l1, l2, rtol=1e-14, atol=1e-14)
+        assert np.allclose(d1, d2, rtol=1e-13, atol=1e-14)
+
+
+def test_oracle_disordered_routes_agree():
+    """Random site disorder breaks every lattice symmetry; route D (pivoted
+    LU per matrix) and route S (spectrum) must still give the same Omega~
+    and gradient."""
+    p = dict(L=4, t=1.0, U=3.0, delta=0.0, T=0.2, n_max=32)
+    phi = uniform(62, 16, -0.5, 0.5)
+    eps = uniform(63, 16, -1.0, 1.0)
+    om_s = oracle.omega_tilde(p, phi, onsite=eps)
+    om_d = oracle.omega_tilde_d(p, phi, onsite=eps)
+    g_s = oracle.grad(p, phi, onsite=eps)
+    g_d = oracle.grad_d(p, phi, onsite=eps)
+    assert abs(om_s - om_d) <= 1e-13 * abs(om_s)
+    assert np.max(np.abs(g_s - g_d)) <= 1e-13 * np.max(np.abs(g_s))
