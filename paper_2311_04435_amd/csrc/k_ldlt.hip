@@ -206,45 +206,42 @@ ldlt_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     }
     __syncthreads();
 
-    // ---- 4. unpivoted LU of the diagonal block by wave 0 (U = D L^T) -----
-    if (w == 0) {
-      for (int k = 0; k < NB; ++k) {
-        const double pr = xsr[k * LDB + k], pi = xsi[k * LDB + k];
-        const double den = pr * pr + pi * pi;
-        const double ir = pr / den, ii = -pi / den;
-        // column k of L (rows below k), one lane per row; row k of U
-        if (lane > k && lane < NB) {
-          const double ar = xsr[lane * LDB + k], ai = xsi[lane * LDB + k];
-          const double lr = ar * ir - ai * ii, li = ar * ii + ai * ir;
-          xsr[lane * LDB + k] = T(lr);
-          xsi[lane * LDB + k] = T(li);
-          lmax = fmax(lmax, fabs(lr) + fabs(li));
-        }
-        if (lane >= k && lane < NB)
-          umax = fmax(umax, (double)fabs(xsr[k * LDB + lane]) +
-                                (double)fabs(xsi[k * LDB + lane]));
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const int m = NB - 1 - k;
-        for (int e = lane; e < m * m; e += 64) {
-          const int i = k + 1 + e / m, j = k + 1 + e % m;
-          const T lr = xsr[i * LDB + k], li = xsi[i * LDB + k];
-          const T ur = xsr[k * LDB + j], ui = xsi[k * LDB + j];
-          xsr[i * LDB + j] -= lr * ur - li * ui;
-          xsi[i * LDB + j] -= lr * ui + li * ur;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+    // ---- 4. unpivoted LU of the diagonal block (U = D L^T), all threads:
+    //         per step k the multipliers of column k, a barrier, the
+    //         rank-1 update of the trailing block, a barrier ---------------
+    for (int k = 0; k < NB; ++k) {
+      const double pr = xsr[k * LDB + k], pi = xsi[k * LDB + k];
+      const double den = pr * pr + pi * pi;
+      const double ir = pr / den, ii = -pi / den;
+      if (tid > k && tid < NB) {
+        const double ar = xsr[tid * LDB + k], ai = xsi[tid * LDB + k];
+        const double lr = ar * ir - ai * ii, li = ar * ii + ai * ir;
+        xsr[tid * LDB + k] = T(lr);
+        xsi[tid * LDB + k] = T(li);
+        lmax = fmax(lmax, fabs(lr) + fabs(li));
       }
-      if (lane < NB) {
-        const double pr = xsr[lane * LDB + lane], pi = xsi[lane * LDB + lane];
-        const double den = pr * pr + pi * pi;
-        bad |= !(den > 0.0) || !isfinite(den);
-        dr_s[c0 + lane] = T(pr);
-        di_s[c0 + lane] = T(pi);
-        er_s[c0 + lane] = T(pr / den);
-        ei_s[c0 + lane] = T(-pi / den);
+      if (tid >= k && tid < NB)
+        umax = fmax(umax, (double)fabs(xsr[k * LDB + tid]) +
+                              (double)fabs(xsi[k * LDB + tid]));
+      __syncthreads();
+      const int m = NB - 1 - k;
+      for (int e = tid; e < m * m; e += NT) {
+        const int i = k + 1 + e / m, j = k + 1 + e % m;
+        const T lr = xsr[i * LDB + k], li = xsi[i * LDB + k];
+        const T ur = xsr[k * LDB + j], ui = xsi[k * LDB + j];
+        xsr[i * LDB + j] -= lr * ur - li * ui;
+        xsi[i * LDB + j] -= lr * ui + li * ur;
       }
+      __syncthreads();
+    }
+    if (tid < NB) {
+      const double pr = xsr[tid * LDB + tid], pi = xsi[tid * LDB + tid];
+      const double den = pr * pr + pi * pi;
+      bad |= !(den > 0.0) || !isfinite(den);
+      dr_s[c0 + tid] = T(pr);
+      di_s[c0 + tid] = T(pi);
+      er_s[c0 + tid] = T(pr / den);
+      ei_s[c0 + tid] = T(-pi / den);
     }
     __syncthreads();
 
