@@ -46,9 +46,18 @@ struct LuLds {
 
 }  // namespace
 
+// row panel: staging chunk width (columns) and staging size (elements of T)
+// per wave
+constexpr int rp_chunk(int waves) { return waves > 8 ? 4 : 8; }
+constexpr int rp_stage_per_wave(int waves) { return 2 * 64 * (rp_chunk(waves) + 1); }
+
 template <typename T>
-size_t lu_lds_bytes(int Np, int NB, int waves) {
+size_t lu_lds_bytes(int Np, int NB, int waves, bool rp = false) {
   size_t b = 0;
+  if (rp) {
+    const long extra = (long)waves * rp_stage_per_wave(waves) - (6L * NB * (NB + 1) + (long)NB * NB);
+    if (extra > 0) b += sizeof(T) * extra;
+  }
   b += sizeof(int) * Np;
   b += sizeof(double) * 2 * waves + sizeof(int) * 2 * waves;
   b += sizeof(double) * 64 * waves;        // final reductions
@@ -60,7 +69,7 @@ size_t lu_lds_bytes(int Np, int NB, int waves) {
   return b + 256;
 }
 
-template <typename T, int WAVES, int RT, int CT>
+template <typename T, int WAVES, int RT, int CT, bool kRP = false>
 __global__ void __launch_bounds__(WAVES * 64)
 lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           int N, int Np, int L, T* __restrict__ F,
@@ -75,8 +84,8 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   extern __shared__ double lds_raw[];
   const int b = blockIdx.x;
   if (only && only[b] != want) return;   // matrix not selected
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int g = lane >> 4, q = lane & 15;
+  const int tid0 = threadIdx.x;
+  const int tid = tid0, lane = tid & 63, w = tid >> 6;
   const int ntiles = Np >> 4;
   const int nblk = Np / NB;
 
@@ -94,6 +103,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     S.lsr = d; d += NB * LD(NB); S.lsi = d; d += NB * LD(NB);
     S.unr = d; d += NB * LD(NB); S.uni = d; d += NB * LD(NB);
     S.tr_ = d; d += NB * NB / 2; S.ti_ = d; d += NB * NB / 2;
+    if (kRP && d < S.xsr + WAVES * rp_stage_per_wave(WAVES)) d = S.xsr + WAVES * rp_stage_per_wave(WAVES);
     int* ip = reinterpret_cast<int*>(d);
     S.crowi = ip; ip += 2 * WAVES;
     S.perm = ip;
@@ -114,6 +124,14 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
 
   for (int J = 0; J < nblk; ++J) {
     const int c0 = J * NB;
+    // row panel: per-block-column copies of the thread indices, so that
+    // values derived from them are not hoisted out of this loop (they would
+    // stay live through every phase and crowd the registers)
+    int tid = tid0;
+    if constexpr (kRP) asm volatile("" : "+v"(tid));
+    const int lane = tid & 63;
+    const int w = kRP ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
+    const int g = lane >> 4, q = lane & 15;
     // ---- 1. generate block column J: X[p][c] = A[perm[p]][c0 + c] ----------
 #pragma unroll
     for (int s = 0; s < RT; ++s) {
@@ -147,9 +165,140 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           xi[s][ct][i] = T(im);
         }
       }
+      // one row tile at a time (hoisting every tile's index loads would
+      // keep all their intermediate values live at once)
+      if constexpr (kRP) __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---- 2. left-looking updates from the previous panels ------------------
+    if constexpr (kRP) {
+    // The A operand of each step (L[rows below panel I][panel I], KPL values
+    // per lane and row tile) and L_II^-1 are loaded one step ahead, so their
+    // latency overlaps the previous step's products and barriers.
+    // prefetch the A operand only while it fits beside the accumulators
+    constexpr bool kPre = RT * KPL <= 16;
+    constexpr int LSPT = (NB * NB + NT - 1) / NT;   // L_II^-1 elements per thread
+    T ar_[RT][KPL], ai_[RT][KPL];
+    T lsr_[LSPT], lsi_[LSPT];
+    auto load_step = [&](int I) {
+      const int r0 = I * NB;
+      {
+        const T* Lr = Tb + (size_t)(I * 4 + 0) * NB * NB;
+#pragma unroll
+        for (int u = 0; u < LSPT; ++u) {
+          const int e = tid + u * NT;
+          if (e < NB * NB) { lsr_[u] = Lr[e]; lsi_[u] = Lr[NB * NB + e]; }
+        }
+      }
+      if constexpr (kPre) {
+#pragma unroll
+      for (int s = 0; s < RT; ++s) {
+        const int t = w + WAVES * s;
+        if (t < ntiles && 16 * t >= r0 + NB) {
+          const int ra = S.perm[16 * t + q];
+          const T* pa_r = Fr + (size_t)ra * Np + r0 + KPL * g;
+          const T* pa_i = Fi + (size_t)ra * Np + r0 + KPL * g;
+#pragma unroll
+          for (int k = 0; k < KPL; ++k) { ar_[s][k] = pa_r[k]; ai_[s][k] = pa_i[k]; }
+        }
+      }
+      }
+    };
+    // the generated block column is complete before the first operand loads
+    // are issued (keeps the loads' registers out of the generation)
+#pragma unroll
+    for (int s = 0; s < RT; ++s)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        asm volatile("" : "+v"(xr[s][ct]), "+v"(xi[s][ct]) :: "memory");
+    if (J > 0) load_step(0);
+    for (int I = 0; I < J; ++I) {
+      const int r0 = I * NB;
+      // (a) panel-I rows of X -> xs; L_II^-1 -> ls
+#pragma unroll
+      for (int s = 0; s < RT; ++s) {
+        const int t = w + WAVES * s;
+        if (t >= (r0 >> 4) && t < ((r0 + NB) >> 4)) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int pr = 16 * t + M::m(g, i) - r0;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              S.xsr[pr * LD(NB) + 16 * ct + q] = xr[s][ct][i];
+              S.xsi[pr * LD(NB) + 16 * ct + q] = xi[s][ct][i];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LSPT; ++u) {
+        const int e = tid + u * NT;
+        if (e < NB * NB) {
+          S.lsr[(e / NB) * LD(NB) + e % NB] = lsr_[u];
+          S.lsi[(e / NB) * LD(NB) + e % NB] = lsi_[u];
+        }
+      }
+      __syncthreads();
+      // (b) un = -(L_II^-1 xs) = -U_IJ ; one 16x16 real output tile per task
+      for (int task = w; task < 2 * CT * CT; task += WAVES) {
+        const int rt = task / (2 * CT), ct = (task >> 1) % CT, part = task & 1;
+        V4 acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int ks = 0; ks < NB / 4; ++ks) {
+          const int k = 4 * ks + g;
+          const T ar = S.lsr[(16 * rt + q) * LD(NB) + k];
+          const T ai = S.lsi[(16 * rt + q) * LD(NB) + k];
+          const T br = S.xsr[k * LD(NB) + 16 * ct + q];
+          const T bi = S.xsi[k * LD(NB) + 16 * ct + q];
+          if (part == 0) { acc = M::mma(ar, br, acc); acc = M::mma(-ai, bi, acc); }
+          else { acc = M::mma(ar, bi, acc); acc = M::mma(ai, br, acc); }
+        }
+        T* dst = part ? S.uni : S.unr;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          dst[(16 * rt + M::m(g, i)) * LD(NB) + 16 * ct + q] = -acc[i];
+      }
+      __syncthreads();
+      // (c) U_IJ to its rows of F; rows below panel I get X += L[:, I] (-U_IJ)
+      for (int e = tid; e < NB * NB; e += NT) {
+        const int rr = e / NB, cc = e % NB;
+        const T ur = -S.unr[rr * LD(NB) + cc], ui = -S.uni[rr * LD(NB) + cc];
+        const size_t o = (size_t)S.perm[r0 + rr] * Np + c0 + cc;
+        Fr[o] = ur;
+        Fi[o] = ui;
+        umax = fmax(umax, (double)fabs(ur) + (double)fabs(ui));
+      }
+#pragma unroll
+      for (int s = 0; s < RT; ++s) {
+        const int t = w + WAVES * s;
+        if (t < ntiles && 16 * t >= r0 + NB) {
+          if constexpr (!kPre) {
+            const int ra = S.perm[16 * t + q];
+            const T* pa_r = Fr + (size_t)ra * Np + r0 + KPL * g;
+            const T* pa_i = Fi + (size_t)ra * Np + r0 + KPL * g;
+#pragma unroll
+            for (int k = 0; k < KPL; ++k) { ar_[s][k] = pa_r[k]; ai_[s][k] = pa_i[k]; }
+          }
+#pragma unroll
+          for (int ks = 0; ks < KPL; ++ks) {
+            const int k = KPL * g + ks;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              const T br = S.unr[k * LD(NB) + 16 * ct + q];
+              const T bi = S.uni[k * LD(NB) + 16 * ct + q];
+              xr[s][ct] = M::mma(ar_[s][ks], br, xr[s][ct]);
+              xr[s][ct] = M::mma(-ai_[s][ks], bi, xr[s][ct]);
+              xi[s][ct] = M::mma(ar_[s][ks], bi, xi[s][ct]);
+              xi[s][ct] = M::mma(ai_[s][ks], br, xi[s][ct]);
+            }
+          }
+        }
+        if constexpr (!kPre) __builtin_amdgcn_sched_barrier(0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (I + 1 < J) load_step(I + 1);
+    }
+    } else {
     for (int I = 0; I < J; ++I) {
       const int r0 = I * NB;
       // (a) panel-I rows of X -> xs; L_II^-1 -> ls
@@ -239,6 +388,181 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       }
     }
 
+    }
+
+    if constexpr (kRP) {
+    // ---- 3. one row per lane: lane L of wave w takes, for k < RPT, row
+    //         L & 15 of its tile s = 4k + L/16 (position 16 (w + WAVES s) +
+    //         L % 16), through a region of LDS private to the wave, CW
+    //         columns at a time
+    constexpr int RPT = (RT + 3) / 4;
+    constexpr int CW = rp_chunk(WAVES);
+    T yr[RPT][NB], yi[RPT][NB];
+    int pos[RPT], org[RPT];
+    T* frow[RPT];   // row of F (re plane; the im plane follows at + plane)
+    T* stg = S.xsr + w * rp_stage_per_wave(WAVES);
+    __syncthreads();   // the staging overlays LDS the update has read
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int s = 4 * k + (lane >> 4);
+      const int p = 16 * (w + WAVES * s) + (lane & 15);
+      const bool live = s < RT && p >= c0 && p < Np;
+      pos[k] = live ? p : -1;
+      org[k] = live ? S.perm[p] : 0;
+      frow[k] = Fr + (size_t)org[k] * Np + c0;
+#pragma unroll
+      for (int cb = 0; cb < NB; cb += CW) {
+        const int ct = cb >> 4, q0 = cb & 15;
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) {
+          const int ss = 4 * k + sl;
+          if (ss < RT) {
+            const int t = w + WAVES * ss;
+            if (t < ntiles && 16 * t + 15 >= c0 && q >= q0 && q < q0 + CW) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int r = 16 * sl + M::m(g, i);
+                stg[2 * (r * (CW + 1) + q - q0)] = xr[ss][ct][i];
+                stg[2 * (r * (CW + 1) + q - q0) + 1] = xi[ss][ct][i];
+              }
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (live) {
+#pragma unroll
+          for (int c = 0; c < CW; ++c) {
+            yr[k][cb + c] = stg[2 * (lane * (CW + 1) + c)];
+            yi[k][cb + c] = stg[2 * (lane * (CW + 1) + c) + 1];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    // ---- 4. panel, one barrier per column.  Rows do not move: a row's
+    //         position changes when it is swapped (pos), its data stays.
+    auto column = [&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      const int pj = c0 + j;
+      const int par = j & 1;
+      // A: best row of this thread, then of the wave (largest |Re|+|Im|,
+      //    lowest position on ties; NaN magnitudes count as 0)
+      double m = -1.0;
+      int mp = 0x7fffffff, mk = 0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        double a = (double)fabs(yr[k][j]) + (double)fabs(yi[k][j]);
+        a = (a >= 0.0) ? a : 0.0;
+        const bool better = pos[k] >= pj && (a > m || (a == m && pos[k] < mp));
+        m = better ? a : m;
+        mp = better ? pos[k] : mp;
+        mk = better ? k : mk;
+      }
+      const double wm = wave_max_d(m);
+      // lowest position among the lanes holding the maximum
+      const int wp = wave_min_i((m == wm) ? mp : 0x7fffffff);
+      const int wl = __ffsll((long long)__ballot(m == wm && mp == wp)) - 1;
+      const int wk = __builtin_amdgcn_readlane(mk, wl);
+      T* slot = S.slr + (par * WAVES + w) * 2 * NB;
+      if (lane == 0) { S.cmag[par * WAVES + w] = wm; S.crowi[par * WAVES + w] = wp; }
+      if (wm >= 0.0 && lane == wl) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          if (k == wk) {
+#pragma unroll
+            for (int c = j; c < NB; ++c) { slot[2 * c] = yr[k][c]; slot[2 * c + 1] = yi[k][c]; }
+          }
+        }
+      }
+      __syncthreads();
+      // B: the winner over the waves and its row (all candidates loaded
+      //    first, then a branch-free selection)
+      double cmv[WAVES];
+      int cpv[WAVES];
+#pragma unroll
+      for (int v = 0; v < WAVES; ++v) { cmv[v] = S.cmag[par * WAVES + v]; cpv[v] = S.crowi[par * WAVES + v]; }
+      double bm = cmv[0];
+      int piv = cpv[0], ww = 0;
+#pragma unroll
+      for (int v = 1; v < WAVES; ++v) {
+        const bool better = (cmv[v] > bm) | ((cmv[v] == bm) & (cpv[v] < piv));
+        bm = better ? cmv[v] : bm;
+        piv = better ? cpv[v] : piv;
+        ww = better ? v : ww;
+      }
+      const T* prow = S.slr + (par * WAVES + ww) * 2 * NB;
+      const double pvr = prow[2 * j], pvi = prow[2 * j + 1];
+      const double rden = 1.0 / (pvr * pvr + pvi * pvi);
+      const T ivr = T(pvr * rden), ivi = T(-pvi * rden);
+      {
+        const int cu = tid < j ? j : (tid < NB ? tid : NB - 1);
+        const double au = (double)fabs(prow[2 * cu]) + (double)fabs(prow[2 * cu + 1]);
+        umax = (tid >= j && tid < NB) ? fmax(umax, au) : umax;
+      }
+      // C: the pivot row moves to position pj, the row at pj to piv
+#pragma unroll
+      for (int k = 0; k < RPT; ++k)
+        pos[k] = (pos[k] == piv) ? pj : (pos[k] == pj ? piv : pos[k]);
+      // D: multipliers of the rows below the pivot (zero elsewhere, which
+      //    leaves those rows unchanged), then the rank-1 update with the
+      //    pivot row read from LDS four columns at a time
+      T lr[RPT], li[RPT];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const bool below = pos[k] > pj;
+        const T ar = yr[k][j], ai = yi[k][j];
+        lr[k] = below ? ar * ivr - ai * ivi : T(0);
+        li[k] = below ? ar * ivi + ai * ivr : T(0);
+        yr[k][j] = below ? lr[k] : ar;
+        yi[k][j] = below ? li[k] : ai;
+      }
+#pragma unroll
+      for (int cg = j + 1; cg < NB; cg += 4) {
+        // compiler barrier: this group's pivot-row loads are not hoisted
+        // above the previous group's products (they would all be live at once)
+        asm volatile("" ::: "memory");
+        T ur[4], ui[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (cg + c < NB) { ur[c] = prow[2 * (cg + c)]; ui[c] = prow[2 * (cg + c) + 1]; }
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (cg + c < NB) {
+              yr[k][cg + c] = fma(-lr[k], ur[c], fma(li[k], ui[c], yr[k][cg + c]));
+              yi[k][cg + c] = fma(-lr[k], ui[c], fma(-li[k], ur[c], yi[k][cg + c]));
+              // keep the products here (not sunk to their next use, which
+              // would keep the loaded pivot row live)
+              asm volatile("" : "+v"(yr[k][cg + c]), "+v"(yi[k][cg + c]));
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    StaticFor<0, NB>::run(column);
+    // ---- 5. rows to F at their original rows, the diagonal block to LDS,
+    //         positions to perm
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      if (pos[k] >= 0) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) { frow[k][c] = yr[k][c]; frow[k][plane + c] = yi[k][c]; }
+        if (pos[k] < c0 + NB) {
+          const int pr = pos[k] - c0;
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            S.xsr[pr * LD(NB) + c] = yr[k][c];
+            S.xsi[pr * LD(NB) + c] = yi[k][c];
+          }
+        }
+        S.perm[pos[k]] = org[k];
+      }
+    }
+    } else {
     // ---- 3. panel factorisation of positions >= c0, one barrier per column
     // Each wave finds its best candidate row for column j and publishes it
     // (|Re|+|Im|, position and the row's values) together with the row now
@@ -426,6 +750,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           }
         }
       }
+    }
     }
     // ---- 6. inverses of the diagonal blocks L_JJ (unit) and U_JJ --------
     __syncthreads();
@@ -733,13 +1058,13 @@ diagdot_kernel(int N, int Np, const T* __restrict__ F,
 
 namespace {
 
-template <typename T, int WAVES, int RT, int CT>
+template <typename T, int WAVES, int RT, int CT, bool kRP = false>
 hipError_t run_lu(const MatDesc* descs, const double* hbuf, int B, int N,
                   int Np, int L, T* F, int* perm, T* tri, double* lad,
                   double* growth, hipStream_t st, const int* only = nullptr,
                   int want = 0) {
-  const size_t lds = lu_lds_bytes<T>(Np, 16 * CT, WAVES);
-  auto kern = lu_kernel<T, WAVES, RT, CT>;
+  const size_t lds = lu_lds_bytes<T>(Np, 16 * CT, WAVES, kRP);
+  auto kern = lu_kernel<T, WAVES, RT, CT, kRP>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
@@ -812,7 +1137,7 @@ hipError_t blocked_lu_f64(const BlockedPlan& p, const MatDesc* descs,
                           hipStream_t st, const int* only, int want) {
   switch (p.cfg) {
     case 0: return run_lu<double, 4, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st, only, want);
-    case 1: return run_lu<double, 8, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st, only, want);
+    case 1: return run_lu<double, 8, 4, 2, true>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st, only, want);
     case 2: return run_lu<double, 16, 4, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st, only, want);
     default: return hipErrorInvalidValue;
   }

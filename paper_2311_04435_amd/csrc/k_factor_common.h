@@ -3,6 +3,7 @@
 // inverses of the two triangles of a diagonal block.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 namespace sca {
 namespace {
@@ -42,6 +43,53 @@ __device__ inline double readlane_d(double v, int lane) {
   const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+// Cross-lane moves inside a row of 16 lanes (DPP controls: 0xB1 and 0x4E
+// are quad permutations [1,0,3,2] and [2,3,0,1], 0x141 mirrors each half
+// row, 0x140 the whole row).  After the four steps in that order every lane
+// of a row has combined all 16 of its row's values.
+template <int C> __device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), C, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int C> __device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, C, 0xF, 0xF, false);
+}
+__device__ inline double dmax(double a, double b) { return a > b ? a : b; }
+
+// Wave maximum of a value that is never NaN (uniform result).
+__device__ inline double wave_max_d(double v) {
+  v = dmax(v, dpp_d<0xB1>(v));
+  v = dmax(v, dpp_d<0x4E>(v));
+  v = dmax(v, dpp_d<0x141>(v));
+  v = dmax(v, dpp_d<0x140>(v));
+  return dmax(dmax(readlane_d(v, 0), readlane_d(v, 16)),
+              dmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
+// Wave minimum of an int (uniform result).
+__device__ inline int wave_min_i(int v) {
+  v = min(v, dpp_i<0xB1>(v));
+  v = min(v, dpp_i<0x4E>(v));
+  v = min(v, dpp_i<0x141>(v));
+  v = min(v, dpp_i<0x140>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// Calls f(integral_constant<int, J>) for J = J0 .. J1-1 in order: a loop over
+// compile-time indices, so register arrays indexed by J stay in registers.
+template <int J0, int J1> struct StaticFor {
+  template <class F> static __device__ __forceinline__ void run(F& f) {
+    f(std::integral_constant<int, J0>{});
+    StaticFor<J0 + 1, J1>::run(f);
+  }
+};
+template <int J1> struct StaticFor<J1, J1> {
+  template <class F> static __device__ __forceinline__ void run(F&) {}
+};
 
 // Inverses of the unit lower and the upper triangle of the NB x NB block
 // (xr, xi; leading dimension NB+1), by recursive doubling: 4x4 leaves by
