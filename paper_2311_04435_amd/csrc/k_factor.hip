@@ -862,15 +862,73 @@ trtri_kernel(int Np, T* __restrict__ F, const int* __restrict__ perm_g,
         ai_[s][ct] = (V4){T(0), T(0), T(0), T(0)};
       }
     const int nsteps = upper ? J : nblk - 1 - J;
-    for (int st = 0; st < nsteps; ++st) {
-      const int I = upper ? st : J + 1 + st;   // block row of U[I,J] / L[I,J]
+    // Loads run ahead of their use: the block X of the next step is fetched
+    // during this step's products, and the A operand of each row tile in two
+    // halves (k < KPL/2, k >= KPL/2), each half fetched while the previous
+    // half's products run.  The active row tiles of a step form a range of
+    // s (the triangle's reach), so the next half is known.
+    constexpr int XE = (NB * NB + NT - 1) / NT;   // block-X elements per thread
+    constexpr int KH = KPL / 2;
+    T xbr[XE], xbi[XE];
+    T abr[2][KH], abi[2][KH];
+    auto step_I = [&](int st) { return upper ? st : J + 1 + st; };
+    auto load_x = [&](int I) {
       const int r0 = I * NB;
+#pragma unroll
+      for (int u = 0; u < XE; ++u) {
+        const int e = tid + u * NT;
+        if (e < NB * NB) {
+          const int orow = perm[r0 + e / NB];
+          xbr[u] = Fr[(size_t)orow * Np + c0 + e % NB];
+          xbi[u] = Fi[(size_t)orow * Np + c0 + e % NB];
+        }
+      }
+    };
+    // tile range [slo, shi) of the rows a step reaches
+    auto tile_range = [&](int I, int& slo, int& shi) {
+      const int r0 = I * NB;
+      int tlo, thi;   // active t in [tlo, thi)
+      if (upper) { tlo = 0; thi = min(c0 >> 4, (r0 + NB + 15) >> 4); }
+      else { tlo = max((c0 + NB) >> 4, r0 >> 4); thi = ntiles; }
+      // s with tlo <= w + WAVES s < thi
+      slo = tlo > w ? (tlo - w + WAVES - 1) / WAVES : 0;
+      shi = thi > w ? (thi - w + WAVES - 1) / WAVES : 0;
+      if (shi > RT) shi = RT;
+    };
+    auto load_a = [&](int I, int s, int h) {
+      const int r0 = I * NB;
+      const int t = w + WAVES * s;
+      const int arow = 16 * t + q;
+      const int orow = perm[arow];
+      const T* pa_r = Fr + (size_t)orow * Np + r0 + KPL * g + KH * h;
+      const T* pa_i = Fi + (size_t)orow * Np + r0 + KPL * g + KH * h;
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int col = r0 + KPL * g + KH * h + k;
+        T vr = pa_r[k], vi = pa_i[k];
+        if (upper) {
+          if (col < arow) { vr = T(0); vi = T(0); }
+        } else {
+          if (col > arow) { vr = T(0); vi = T(0); }
+          else if (col == arow) { vr = T(1); vi = T(0); }
+        }
+        abr[h][k] = vr; abi[h][k] = vi;
+      }
+    };
+    if (nsteps > 0) load_x(step_I(0));
+    for (int st = 0; st < nsteps; ++st) {
+      const int I = step_I(st);
+      int slo, shi;
+      tile_range(I, slo, shi);
+      if (slo < shi) load_a(I, slo, 0);   // first half, ahead of the Y products
       __syncthreads();
-      for (int e = tid; e < NB * NB; e += NT) {
-        const int rr = e / NB, cc = e % NB;
-        const int orow = perm[r0 + rr];
-        xsr[rr * LD(NB) + cc] = Fr[(size_t)orow * Np + c0 + cc];
-        xsi[rr * LD(NB) + cc] = Fi[(size_t)orow * Np + c0 + cc];
+#pragma unroll
+      for (int u = 0; u < XE; ++u) {
+        const int e = tid + u * NT;
+        if (e < NB * NB) {
+          xsr[(e / NB) * LD(NB) + e % NB] = xbr[u];
+          xsi[(e / NB) * LD(NB) + e % NB] = xbi[u];
+        }
       }
       __syncthreads();
       // Y = X_blk * D  (D = U_JJ^-1 or L_JJ^-1)
@@ -893,45 +951,32 @@ trtri_kernel(int Np, T* __restrict__ F, const int* __restrict__ perm_g,
           dst[(16 * rt + M::m(g, i)) * LD(NB) + 16 * ct + q] = acc[i];
       }
       __syncthreads();
+      if (st + 1 < nsteps) load_x(step_I(st + 1));
       // acc[rows] += Tri[rows, I-cols] * Y, rows in the triangle's reach
 #pragma unroll
       for (int s = 0; s < RT; ++s) {
-        const int t = w + WAVES * s;
-        const bool active = upper ? (t < (c0 >> 4) && 16 * t < r0 + NB)
-                                  : (t < ntiles && t >= ((c0 + NB) >> 4) && 16 * t + 15 >= r0);
-        if (active) {
-          const int arow = 16 * t + q;     // A-operand row (position)
-          const int orow = perm[arow];
-          const T* pa_r = Fr + (size_t)orow * Np + r0 + KPL * g;
-          const T* pa_i = Fi + (size_t)orow * Np + r0 + KPL * g;
-          T a_r[KPL], a_i[KPL];
+        if (s >= slo && s < shi) {
 #pragma unroll
-          for (int k = 0; k < KPL; ++k) {
-            const int col = r0 + KPL * g + k;
-            T vr = pa_r[k], vi = pa_i[k];
-            if (upper) {
-              if (col < arow) { vr = T(0); vi = T(0); }
-            } else {
-              if (col > arow) { vr = T(0); vi = T(0); }
-              else if (col == arow) { vr = T(1); vi = T(0); }
+          for (int h = 0; h < 2; ++h) {
+            // fetch the next half while this one's products run
+            if (h == 0) load_a(I, s, 1);
+            else if (s + 1 < shi) load_a(I, s + 1, 0);
+#pragma unroll
+            for (int kk = 0; kk < KH; ++kk) {
+              const int k = KPL * g + KH * h + kk;
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) {
+                const T b_r = yr_s[k * LD(NB) + 16 * ct + q];
+                const T b_i = yi_s[k * LD(NB) + 16 * ct + q];
+                ar_[s][ct] = M::mma(abr[h][kk], b_r, ar_[s][ct]);
+                ar_[s][ct] = M::mma(-abi[h][kk], b_i, ar_[s][ct]);
+                ai_[s][ct] = M::mma(abr[h][kk], b_i, ai_[s][ct]);
+                ai_[s][ct] = M::mma(abi[h][kk], b_r, ai_[s][ct]);
+              }
             }
-            a_r[k] = vr; a_i[k] = vi;
-          }
-#pragma unroll
-          for (int ks = 0; ks < KPL; ++ks) {
-            const int k = KPL * g + ks;
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-              const T b_r = yr_s[k * LD(NB) + 16 * ct + q];
-              const T b_i = yi_s[k * LD(NB) + 16 * ct + q];
-              ar_[s][ct] = M::mma(a_r[ks], b_r, ar_[s][ct]);
-              ar_[s][ct] = M::mma(-a_i[ks], b_i, ar_[s][ct]);
-              ai_[s][ct] = M::mma(a_r[ks], b_i, ai_[s][ct]);
-              ai_[s][ct] = M::mma(a_i[ks], b_r, ai_[s][ct]);
-            }
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
-        __builtin_amdgcn_sched_barrier(0);
       }
     }
     __syncthreads();
