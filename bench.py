@@ -47,11 +47,11 @@ HBM_PEAK = 8000.0                       # GB/s
 # counters were taken on: a changed source reports null.
 TRAFFIC = {
     ("lu", "hubbard_20x20_T0.1", "fp64", "lu"): (
-        15.912e9, "k_factor.hip",
-        "e726ac3eb3b7c15a071e493dad5ab794d719520546b9b75057d3dcea8d9855c8"),
+        26.867e9, "k_factor.hip",
+        "663c80d764eaf46a9ac244abdfe4e97e21d1156fba337cad212e6132c3371679"),
     ("ldlt", "hubbard_20x20_T0.1", "fp64", "ldlt"): (
-        8.095e9, "k_ldlt.hip",
-        "0a670676091fa10f07b4abf65fb2423ee0910818fea3802d2cefc7383488c71d"),
+        8.093e9, "k_ldlt.hip",
+        "4cf959a57de490a72fb2705cb64b0f9c8a9a37292161af1ff71b6f28f1ef2ca2"),
 }
 
 
