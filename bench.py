@@ -19,6 +19,9 @@ Prints one JSON line.  Besides the contract fields it carries
   symmetric_ldlt the same workload on the symmetric route (unpivoted
                 L D L^T, exact for these complex symmetric matrices, half
                 the flops) with its own roofline;
+  tail          the same workload with only the low Matsubara frequencies
+                factorised and the rest from the moments of H (pivoted LU,
+                then symmetric), with n_factorised and their rooflines;
   serving       served solves/s and p50/p99 latency of a Poisson stream of
                 mixed requests through the request server, next to the
                 one-at-a-time FIFO baseline on the same GPU.
@@ -137,12 +140,13 @@ def cpu_baseline(wl, budget_s: float):
             "route_s_steps_per_s": route_s}
 
 
-def workload_rate(sca, name, prec, steps, warmup, factor="lu"):
+def workload_rate(sca, name, prec, steps, warmup, factor="lu", tail=False):
     """Timed ADAM steps of a named workload (phi, m, v resident on the GPU)."""
     import torch
     import synth
     wl = synth.WORKLOADS[name]
-    p = sca.Params.from_dict(wl["params"], precision=prec, factor=factor)
+    p = sca.Params.from_dict(wl["params"], precision=prec, factor=factor,
+                             tail=tail)
     hy = wl["adam"]
     phi = torch.as_tensor(synth.make_phi0(p.L, wl["phi0"]),
                           dtype=torch.float64).cuda()
@@ -156,19 +160,24 @@ def workload_rate(sca, name, prec, steps, warmup, factor="lu"):
     ctx.adam_solve(p, phi, m, v, steps, t0=warmup, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"workload": name, "precision": prec, "factor": factor,
-            "steps": steps,
-            "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps}
+    out = {"workload": name, "precision": prec, "factor": factor,
+           "steps": steps,
+           "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps}
+    if tail:
+        out["tail"] = True
+        out["n_factorised"] = sca.tail_split(p, phi)
+    return out
 
 
-def route_line(sca, name, prec, factor, steps, warmup):
+def route_line(sca, name, prec, factor, steps, warmup, tail=False):
     """Steps/s of a workload on a given route, with the per-kernel averages
     (HIP events) and the roofline of its dominant kernel."""
-    out = workload_rate(sca, name, prec, steps, warmup, factor)
+    out = workload_rate(sca, name, prec, steps, warmup, factor, tail)
     import torch
     import synth
     wl = synth.WORKLOADS[name]
-    p = sca.Params.from_dict(wl["params"], precision=prec, factor=factor)
+    p = sca.Params.from_dict(wl["params"], precision=prec, factor=factor,
+                             tail=tail)
     phi = torch.as_tensor(synth.make_phi0(p.L, wl["phi0"]),
                           dtype=torch.float64).cuda()
     ctx = sca.Context()
@@ -177,13 +186,14 @@ def route_line(sca, name, prec, factor, steps, warmup):
     kw = dict(lr=hy["lr"], beta1=hy["beta1"], beta2=hy["beta2"], eps=hy["eps"],
               final_eval=False)
     ctx.adam_solve(p, phi, m, v, warmup, **kw)
+    n_fact = sca.tail_split(p, phi)   # frequencies factorised in this call
     ctx.profile(True)
     ctx.adam_solve(p, phi, m, v, steps, t0=warmup, **kw)
     prof = ctx.profile_read()
     ctx.profile(False)
     out["kernels"] = {k: {"avg_ms": ms / n, "launches": n} for k, (ms, n) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])
-    N, B = p.L * p.L, 2 * p.n_max
+    N, B = p.L * p.L, 2 * n_fact
     work = kernel_work(dom, N, B)
     if work is not None:
         amount, unit, bound = work
@@ -194,15 +204,15 @@ def route_line(sca, name, prec, factor, steps, warmup):
             out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": ach,
                                "peak": peak, "unit": "TFLOP/s",
                                "frac": ach / peak,
-                               "traffic": measured_traffic(dom, name, prec,
-                                                           factor)}
+                               "traffic": None if tail else
+                               measured_traffic(dom, name, prec, factor)}
         else:
             ach = amount / avg_s / 1e9
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach,
                                "peak": HBM_PEAK, "unit": "GB/s",
                                "frac": ach / HBM_PEAK,
-                               "traffic": measured_traffic(dom, name, prec,
-                                                           factor)}
+                               "traffic": None if tail else
+                               measured_traffic(dom, name, prec, factor)}
     return out
 
 
@@ -273,6 +283,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-l32", action="store_true")
+    ap.add_argument("--no-tail", action="store_true",
+                    help="skip the Matsubara-tail lines")
     ap.add_argument("--no-symmetric", action="store_true",
                     help="skip the symmetric-route line")
     ap.add_argument("--serving-requests", type=int, default=32,
@@ -397,6 +409,11 @@ def main():
         # the same workload on the symmetric route (unpivoted L D L^T)
         out["symmetric_ldlt"] = route_line(sca, args.workload, "fp64", "ldlt",
                                            max(args.steps, 10), args.warmup)
+    if prec == "fp64" and not args.no_tail:
+        # the same sums with the high frequencies from the moments of H
+        out["tail"] = [route_line(sca, args.workload, "fp64", f,
+                                  max(args.steps, 20), args.warmup, tail=True)
+                       for f in ("lu", "ldlt")]
     if args.serving_requests > 0:
         Ls = tuple(int(x) for x in args.serving_L.split(","))
         out["serving"] = serving(sca, args.serving_requests, args.serving_steps,

@@ -78,6 +78,30 @@ typedef enum { SCA_FP64 = 0, SCA_FP32_REFINED = 1 } sca_precision;
  *                    FP64 only (SCA_EUNSUPPORTED with SCA_FP32_REFINED). */
 typedef enum { SCA_FACTOR_LU = 0, SCA_FACTOR_LDLT = 1 } sca_factor;
 
+/* Matsubara frequencies that are factorised.
+ *   SCA_TAIL_NONE     all n < n_max (the default).
+ *   SCA_TAIL_MOMENTS  only n < n_c; for n_c <= n < n_max the terms come from
+ *                     the moments of H: for w > rho(H),
+ *                       ln|det(i w - H)| = N ln w
+ *                           + 1/2 sum_{m>=1} (-1)^(m+1)/m tr(H^2m) w^-2m,
+ *                       Re (i w - H)^-1_ii = -sum_{m>=0} (-1)^m (H^(2m+1))_ii
+ *                           w^-(2m+2),
+ *                     each cut after 14 terms.  n_c is the first n with
+ *                     w_n >= 4 rho_b, rho_b = 4|t| + |delta|/2 + max|onsite|
+ *                     + max(max|phi|, U/2) + 1/2 (a Gershgorin bound with a
+ *                     margin for phi to grow during a solve), at least 1.
+ *                     While every pass's Gershgorin bound stays below
+ *                     w_{n_c}/3 the truncation error of each term is below
+ *                     9^-15 of its scale; a pass above it sets
+ *                     SCA_FLAG_TAIL_RANGE (sca_potential and sca_grad then
+ *                     re-evaluate without the tail; sca_adam_solve runs the
+ *                     remaining steps without it from the check that saw
+ *                     the flag).  The same sums are computed, only the
+ *                     evaluation of the high frequencies differs.  Not
+ *                     available for sca_factorize / sca_grad_from_factors or
+ *                     the request server (SCA_EUNSUPPORTED). */
+typedef enum { SCA_TAIL_NONE = 0, SCA_TAIL_MOMENTS = 1 } sca_tail;
+
 /* One SCA problem.  onsite: optional DEVICE array of N extra site
  * potentials (a disordered lattice), or NULL (the paper's ionic model). */
 typedef struct {
@@ -87,6 +111,8 @@ typedef struct {
   int32_t factor;     /* sca_factor */
   double t, U, delta, T;
   const double* onsite;
+  int32_t tail;       /* sca_tail */
+  int32_t reserved;   /* 0 */
 } sca_params;
 
 typedef struct {
@@ -119,6 +145,7 @@ typedef struct {
 #define SCA_FLAG_NONFINITE 1    /* a non-finite value was produced */
 #define SCA_FLAG_PIVOT_GROWTH 2 /* FP32 growth above 1e3 (see above) */
 #define SCA_FLAG_CONVERGED 4    /* stopped by grad_tol */
+#define SCA_FLAG_TAIL_RANGE 8   /* a pass exceeded the tail's spectral guard */
 
 /* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`
  * (a hipStream_t; NULL = the null stream).  hbm_budget_bytes bounds the

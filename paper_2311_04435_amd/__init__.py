@@ -21,7 +21,7 @@ import torch
 from . import _lib
 from ._lib import (SCAError, SCA_FP64, SCA_FP32_REFINED,  # noqa: F401
                    SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH,
-                   SCA_FLAG_CONVERGED)
+                   SCA_FLAG_CONVERGED, SCA_FLAG_TAIL_RANGE)
 
 PRECISIONS = {"fp64": SCA_FP64, "fp32r": SCA_FP32_REFINED}
 FACTORS = {"lu": _lib.SCA_FACTOR_LU, "ldlt": _lib.SCA_FACTOR_LDLT}
@@ -33,8 +33,11 @@ class Params:
     ionic amplitude delta (site potential +-delta/2), temperature T > 0,
     n_max Matsubara frequencies per sign, precision 'fp64' | 'fp32r',
     factorisation 'lu' (pivoted, default) | 'ldlt' (symmetric, unpivoted,
-    FP64) and an optional extra site potential `onsite` (float64 CUDA tensor
-    of N)."""
+    FP64), an optional extra site potential `onsite` (float64 CUDA tensor
+    of N) and `tail`: factorise only the Matsubara frequencies below about
+    4x a bound on the spectral radius of H and take the rest from the
+    moments of H (the same sums, evaluated by a series whose truncation
+    error the library keeps below 9^-15 of each term's scale)."""
     L: int
     U: float
     T: float
@@ -44,6 +47,7 @@ class Params:
     precision: str = "fp64"
     onsite: Optional[torch.Tensor] = None
     factor: str = "lu"
+    tail: bool = False
 
     @property
     def N(self) -> int:
@@ -59,7 +63,9 @@ class Params:
             ons = _dev(self.onsite, self.N, "onsite").data_ptr()
         return _lib.Params(self.L, self.n_max, PRECISIONS[self.precision],
                            FACTORS[self.factor], self.t, self.U, self.delta,
-                           self.T, ons)
+                           self.T, ons,
+                           _lib.SCA_TAIL_MOMENTS if self.tail else _lib.SCA_TAIL_NONE,
+                           0)
 
     @classmethod
     def from_dict(cls, d: dict, precision: str = "fp64", **kw) -> "Params":
@@ -230,6 +236,19 @@ def adam_solve(p: Params, phi0: torch.Tensor, n_steps: int, **kw):
     v = torch.zeros_like(phi)
     res = default_context().adam_solve(p, phi, m, v, n_steps, **kw)
     return phi, m, v, res
+
+
+def tail_split(p: Params, phi: torch.Tensor) -> int:
+    """Number of Matsubara frequencies the library factorises for p at phi
+    under Params(tail=True) (the rule of include/sca.h, SCA_TAIL_MOMENTS)."""
+    import math
+    if not p.tail:
+        return p.n_max
+    pmax = float(phi.abs().max())
+    omax = float(p.onsite.abs().max()) if p.onsite is not None else 0.0
+    rho = 4 * abs(p.t) + 0.5 * abs(p.delta) + omax + max(pmax, 0.5 * p.U) + 0.5
+    x = (4 * rho / (math.pi * p.T) - 1) / 2
+    return p.n_max if x >= p.n_max else max(1, math.ceil(x))
 
 
 def dos(p: Params, phi: torch.Tensor, w: torch.Tensor, eta: float = 0.05):

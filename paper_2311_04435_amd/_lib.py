@@ -18,11 +18,13 @@ STATUS_NAMES = {0: "SCA_OK", -1: "SCA_EINVAL", -2: "SCA_ENOMEM",
 SCA_FP64, SCA_FP32_REFINED = 0, 1
 SCA_FACTOR_LU, SCA_FACTOR_LDLT = 0, 1
 SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH, SCA_FLAG_CONVERGED = 1, 2, 4
+SCA_FLAG_TAIL_RANGE = 8
+SCA_TAIL_NONE, SCA_TAIL_MOMENTS = 0, 1
 SCA_ADAM_NO_FINAL_EVAL = 1
 PROFILE_SLOTS = 16
 KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
                   "refine", "wvgemm", "ldlt", "trtri_sym", "symdiag",
-                  "fallback", "spare12", "spare13", "spare14", "spare15")
+                  "fallback", "tail", "spare13", "spare14", "spare15")
 
 # Every symbol include/sca.h declares.
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",
@@ -37,7 +39,8 @@ class Params(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_max", C.c_int32),
                 ("precision", C.c_int32), ("factor", C.c_int32),
                 ("t", C.c_double), ("U", C.c_double), ("delta", C.c_double),
-                ("T", C.c_double), ("onsite", C.c_void_p)]
+                ("T", C.c_double), ("onsite", C.c_void_p),
+                ("tail", C.c_int32), ("reserved", C.c_int32)]
 
 
 class AdamOpts(C.Structure):

@@ -52,8 +52,8 @@ __global__ void matsubara_desc_kernel(const ProbDesc* __restrict__ probs,
   const int p = blockIdx.y;
   const ProbDesc P = probs[p];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= 2 * P.M) return;
-  const int sidx = k / P.M, n = k % P.M;
+  if (k >= 2 * P.Me) return;
+  const int sidx = k / P.Me, n = k % P.Me;
   MatDesc d;
   d.zr = 0.0;
   d.zi = (2.0 * n + 1.0) * kPi * P.T;
@@ -77,13 +77,15 @@ struct ChunkPartial {
   double phi2;      // sum phi_i^2 (phi at which the terms were evaluated)
   double stag;      // sum (-1)^(x+y) phi_i
   double gmax;      // max |g_i|
+  double hmax;      // max_i max_s |h_i| (Gershgorin bound of the tail guard)
   int32_t nonfinite, pad_;
 };
 
 __global__ void __launch_bounds__(kReduceThreads)
 site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
                    const double* __restrict__ dg, ChunkPartial* __restrict__ part,
-                   int adam) {
+                   int adam, const double* __restrict__ mom,
+                   const double* __restrict__ tsum) {
   const int p = blockIdx.y;
   const int chunk = blockIdx.x;
   const ProbDesc P = probs[p];
@@ -92,14 +94,14 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
   const int bpart = tid / kSitesPerBlock;
   const int i = chunk * kSitesPerBlock + site_l;
   __shared__ double acc_s[kBParts][kSitesPerBlock];
-  __shared__ double red_s[3][kSitesPerBlock];
+  __shared__ double red_s[4][kSitesPerBlock];
   __shared__ int nf_s[kSitesPerBlock];
 
-  // sum over the problem's 2M matrices, split in kBParts contiguous ranges
+  // sum over the problem's 2 Me matrices, split in kBParts contiguous ranges
   // per spin; each range summed in increasing n
   double acc = 0.0;
   if (i < N && dg) {
-    const int M = P.M;
+    const int M = P.Me;
     const int per = (M + kBParts - 1) / kBParts;
     const int n0 = bpart * per, n1 = min(M, n0 + per);
     double su = 0.0, sd = 0.0;
@@ -112,12 +114,31 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
   acc_s[bpart][site_l] = acc;
   __syncthreads();
   if (bpart == 0) {
-    double phi2 = 0.0, stag = 0.0, ga = 0.0;
+    double phi2 = 0.0, stag = 0.0, ga = 0.0, hm = 0.0;
     int nf = 0;
     if (i < N) {
       double s = acc_s[0][site_l];
       for (int q = 1; q < kBParts; ++q) s += acc_s[q][site_l];
       const double ph = P.phi[i];
+      if (P.Me < P.M) {
+        double a = 0.5 * P.delta * (double)stagger_sign(i, P.L);
+        if (P.onsite) a += P.onsite[i];
+        hm = fabs(a) + fabs(ph);
+      }
+      if (P.Me < P.M && dg) {
+        // tail: sum_{n >= Me} Re G_ii = -sum_m (-1)^m (H^(2m+1))_ii S_{2m+2},
+        // up minus down
+        const double* ts = tsum + (size_t)p * kTailS;
+        const double* mu = mom + (size_t)p * 2 * kTailP * N + i;
+        const double* md = mu + (size_t)kTailP * N;
+        double tu = 0.0, td = 0.0;
+        for (int m = kTailK; m >= 0; --m) {
+          const double sg = (m & 1) ? -1.0 : 1.0;
+          tu += sg * mu[(size_t)(2 * m) * N] * ts[m + 1];
+          td += sg * md[(size_t)(2 * m) * N] * ts[m + 1];
+        }
+        s += td - tu;
+      }
       const double g = dg ? 2.0 * ph / P.U - 2.0 * P.T * s : 0.0;
       if (P.grad && dg) P.grad[i] = g;
       phi2 = ph * ph;
@@ -141,20 +162,22 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
     red_s[0][site_l] = phi2;
     red_s[1][site_l] = stag;
     red_s[2][site_l] = ga;
+    red_s[3][site_l] = hm;
     nf_s[site_l] = nf;
   }
   __syncthreads();
   if (tid == 0) {
-    double a = 0.0, b = 0.0, c = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0, h = 0.0;
     int nf = 0;
     for (int q = 0; q < kSitesPerBlock; ++q) {
       a += red_s[0][q];
       b += red_s[1][q];
       c = fmax(c, red_s[2][q]);
+      h = fmax(h, red_s[3][q]);
       nf |= nf_s[q];
     }
     ChunkPartial cp;
-    cp.phi2 = a; cp.stag = b; cp.gmax = c; cp.nonfinite = nf; cp.pad_ = 0;
+    cp.phi2 = a; cp.stag = b; cp.gmax = c; cp.hmax = h; cp.nonfinite = nf; cp.pad_ = 0;
     part[p * kMaxChunks + chunk] = cp;
   }
 }
@@ -164,20 +187,38 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
                       const double* __restrict__ lad,
                       const double* __restrict__ growth,
                       const ChunkPartial* __restrict__ part, int nchunks,
-                      ProbStats* __restrict__ stats, int advance) {
+                      ProbStats* __restrict__ stats, int advance,
+                      const double* __restrict__ mom,
+                      const double* __restrict__ tsum) {
   const int p = blockIdx.x;
   const ProbDesc P = probs[p];
   const int tid = threadIdx.x;
   __shared__ double s_full[256], s_red[256], s_gr[256];
   // each thread sums a strided subset of the 2M matrices in increasing b
   double full = 0.0, red = 0.0, gr = 0.0;
-  for (int k = tid; k < 2 * P.M; k += 256) {
-    const int n = k % P.M;
+  for (int k = tid; k < 2 * P.Me; k += 256) {
+    const int n = k % P.Me;
     const double w = (2.0 * n + 1.0) * kPi * P.T;
     const double l = lad[P.mat_begin + k];
     full += l;
     red += l - (double)N * log(w);
     gr = fmax(gr, growth[P.mat_begin + k]);
+  }
+  if (P.Me < P.M) {
+    // tail of both spins: 1/2 sum_m (-1)^(m+1)/m tr(H^2m) S_2m, plus
+    // N sum_n ln w_n in the full sum
+    const double* ts = tsum + (size_t)p * kTailS;
+    const double* mb = mom + (size_t)p * 2 * kTailP * N;
+    for (int i = tid; i < N; i += 256) {
+      double r = 0.0;
+      for (int sidx = 0; sidx < 2; ++sidx)
+        for (int m = kTailK; m >= 1; --m)
+          r += ((m & 1) ? 0.5 : -0.5) / m * ts[m] *
+               mb[((size_t)sidx * kTailP + 2 * m - 1) * N + i];
+      red += r;
+      full += r;
+    }
+    if (tid == 0) full += 2.0 * (double)N * ts[0];
   }
   s_full[tid] = full; s_red[tid] = red; s_gr[tid] = gr;
   __syncthreads();
@@ -190,11 +231,12 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
     __syncthreads();
   }
   if (tid == 0) {
-    double phi2 = 0.0, stag = 0.0, gmax = 0.0;
+    double phi2 = 0.0, stag = 0.0, gmax = 0.0, hmax = 0.0;
     int nf = 0;
     for (int c = 0; c < nchunks; ++c) {
       const ChunkPartial cp = part[p * kMaxChunks + c];
       phi2 += cp.phi2; stag += cp.stag; gmax = fmax(gmax, cp.gmax);
+      hmax = fmax(hmax, cp.hmax);
       nf |= cp.nonfinite;
     }
     ProbStats S;
@@ -205,7 +247,7 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
     S.pivot_growth = s_gr[0];
     nf |= !isfinite(S.omega) || !isfinite(S.omega_tilde);
     S.nonfinite = nf;
-    S.pad_ = 0;
+    S.tail_range = (P.Me < P.M && !(hmax + 4.0 * fabs(P.t) <= P.tail_guard)) ? 1 : 0;
     stats[p] = S;
     // the site kernel of this pass has read adam_t and steps_left already
     if (advance && P.steps_left > 0) {
@@ -224,6 +266,7 @@ int reduce_max_sites() { return kSitesPerBlock * kMaxChunks; }
 hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
                          const double* dg, const double* growth,
                          ProbStats* stats, bool adam, void* ws,
+                         const double* mom, const double* tsum,
                          hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
   const int nchunks = (N + kSitesPerBlock - 1) / kSitesPerBlock;
@@ -232,12 +275,12 @@ hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
   mark_begin(K_REDUCE, st);
   hipLaunchKernelGGL(site_reduce_kernel, dim3(nchunks, nprob),
                      dim3(kReduceThreads), 0, st, probs, N, dg, part,
-                     (int)adam);
+                     (int)adam, mom, tsum);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(problem_reduce_kernel, dim3(nprob), dim3(256), 0, st,
                      probs, N, lad, growth, part, nchunks, stats,
-                     (int)(adam && dg != nullptr));
+                     (int)(adam && dg != nullptr), mom, tsum);
   mark_end(K_REDUCE, st);
   return hipGetLastError();
 }

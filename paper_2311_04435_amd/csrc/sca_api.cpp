@@ -41,6 +41,10 @@ sca_status fail(sca_status s, const char* fmt, ...) {
 
 #define HIP_TRY SCA_HIP_TRY
 
+namespace {
+constexpr double kPiHost = 3.14159265358979323846;
+}
+
 struct sca_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -49,6 +53,7 @@ struct sca_ctx {
   size_t ws_bytes = 0;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  double* dscalar = nullptr;   // one device double (tail planning)
   sca::Profiler prof;
 };
 
@@ -64,6 +69,9 @@ sca_status validate_params(const sca_params* p) {
     return fail(SCA_EINVAL, "precision=%d: unknown", p->precision);
   if (p->factor != SCA_FACTOR_LU && p->factor != SCA_FACTOR_LDLT)
     return fail(SCA_EINVAL, "factor=%d: unknown", p->factor);
+  if (p->tail != SCA_TAIL_NONE && p->tail != SCA_TAIL_MOMENTS)
+    return fail(SCA_EINVAL, "tail=%d: unknown", p->tail);
+  if (p->reserved != 0) return fail(SCA_EINVAL, "reserved must be 0");
   if (!std::isfinite(p->t) || !std::isfinite(p->delta))
     return fail(SCA_EINVAL, "t and delta must be finite");
   if (!(p->U > 0.0) || !std::isfinite(p->U))
@@ -122,6 +130,8 @@ ProbDesc make_prob(const sca_params* p, const double* phi, double* grad) {
   P.grad = grad;
   P.t = p->t; P.U = p->U; P.delta = p->delta; P.T = p->T;
   P.L = p->L; P.N = p->L * p->L; P.M = p->n_max;
+  P.Me = p->n_max;
+  P.tail_guard = 0.0;
   P.mat_begin = 0;
   P.hoff = 0;
   return P;
@@ -131,12 +141,14 @@ hipError_t enqueue_pass(const Carve& c, int nprob, int L, int B,
                         int precision, bool adam, hipStream_t st) {
   const int N = L * L;
   hipError_t e = launch_hvec(c.probs, nprob, N, c.hbuf, st);
+  if (e == hipSuccess && c.tail_on)
+    e = launch_tail(c.probs, nprob, N, c.hbuf, c.mom, c.tsum, st);
   if (e == hipSuccess)
     e = factor_batch(c.descs, c.hbuf, B, N, L, precision, c.lad, c.dg,
                      c.growth, c.fact, st);
   if (e == hipSuccess)
     e = launch_reduce(c.probs, nprob, N, c.lad, c.dg, c.growth, c.stats, adam,
-                      c.rws, st);
+                      c.rws, c.mom, c.tsum, st);
   return e;
 }
 
@@ -178,6 +190,42 @@ sca_status ensure_pinned(sca_ctx* ctx, size_t bytes) {
   ctx->pinned_bytes = 0;
   HIP_TRY(hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
   ctx->pinned_bytes = bytes;
+  return SCA_OK;
+}
+
+sca_status device_absmax(sca_ctx* ctx, const double* x, int n, double* out) {
+  if (!ctx->dscalar) HIP_TRY(hipMalloc(&ctx->dscalar, sizeof(double)));
+  sca_status s = ensure_pinned(ctx, sizeof(double));
+  if (s) return s;
+  HIP_TRY(launch_absmax(x, n, ctx->dscalar, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, ctx->dscalar, sizeof(double),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  std::memcpy(out, ctx->pinned, sizeof(double));
+  return SCA_OK;
+}
+
+// Frequencies factorised under SCA_TAIL_MOMENTS: n < Me, the first n with
+// w_n >= 4 rho_b (rho_b: Gershgorin bound with a margin for phi to grow);
+// each pass flags a bound above w_Me / 3.
+sca_status plan_tail(sca_ctx* ctx, const sca_params* p, const double* phi,
+                     ProbDesc& P) {
+  P.Me = p->n_max;
+  P.tail_guard = 0.0;
+  if (p->tail != SCA_TAIL_MOMENTS) return SCA_OK;
+  const int N = p->L * p->L;
+  double pmax = 0.0, omax = 0.0;
+  sca_status s = device_absmax(ctx, phi, N, &pmax);
+  if (s) return s;
+  if (p->onsite && (s = device_absmax(ctx, p->onsite, N, &omax))) return s;
+  if (!std::isfinite(pmax) || !std::isfinite(omax))
+    return fail(SCA_ENUMERIC, "phi or onsite is not finite");
+  const double phib = std::max(pmax, 0.5 * p->U) + 0.5;
+  const double rho = 4.0 * std::fabs(p->t) + 0.5 * std::fabs(p->delta) + omax + phib;
+  const double x = (4.0 * rho / (kPiHost * p->T) - 1.0) / 2.0;
+  const int me = x >= (double)p->n_max ? p->n_max : std::max(1, (int)std::ceil(x));
+  P.Me = me;
+  P.tail_guard = (2.0 * me + 1.0) * kPiHost * p->T / 3.0;
   return SCA_OK;
 }
 
@@ -228,6 +276,9 @@ Carve carve(char* base, int nprob, int N, int B, int precision,
   c.dg = own_dg ? (double*)take(sizeof(double) * 2 * (size_t)B * N) : nullptr;
   c.rws = take(reduce_workspace_bytes(nprob));
   c.stats = (ProbStats*)take(sizeof(ProbStats) * nprob);
+  c.mom = (double*)take(tail_workspace_bytes(nprob, N));
+  c.tsum = c.mom ? c.mom + (size_t)nprob * 2 * kTailP * N : nullptr;
+  c.tail_on = false;
   c.fact = fact_bytes ? (void*)take(fact_bytes) : nullptr;
   (void)precision;
   c.total = off;
@@ -299,19 +350,28 @@ bool growth_exceeded(int mode, double growth) {
 
 sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
                        double* grad, double* omega2, ProbStats* st_out) {
-  const int N = p->L * p->L, M = p->n_max, B = 2 * M;
+  const int N = p->L * p->L;
+  ProbDesc P = make_prob(p, phi, grad);
+  sca_status s = plan_tail(ctx, p, phi, P);
+  if (s) return s;
+  const int B = 2 * P.Me;
   Carve c0 = carve(nullptr, 1, N, B, route_of(p), true, true,
                    factor_workspace_bytes(N, B, route_of(p)));
-  sca_status s = ensure_ws(ctx, c0.total);
-  if (s) return s;
+  if ((s = ensure_ws(ctx, c0.total))) return s;
   Carve c = carve((char*)ctx->ws, 1, N, B, route_of(p), true, true,
                   factor_workspace_bytes(N, B, route_of(p)));
-  ProbDesc P = make_prob(p, phi, grad);
+  c.tail_on = P.Me < P.M;
   s = run_batch(ctx, c, &P, 1, p->L, B, B, route_of(p), false, true);
   if (s) return s;
   ProbStats S;
   s = read_stats(ctx, c, 1, &S);
   if (s) return s;
+  if (S.tail_range) {
+    // the spectral bound left the tail's range: evaluate every frequency
+    sca_params q = *p;
+    q.tail = SCA_TAIL_NONE;
+    return eval_single(ctx, &q, phi, grad, omega2, st_out);
+  }
   if (growth_exceeded(route_of(p), S.pivot_growth) && !S.nonfinite) {
     if (!path_supported(N, route_of(p) & ~kModeFp32))
       return fail(SCA_ENUMERIC, "FP32 pivot growth %.3g above %.0e and no "
@@ -370,6 +430,7 @@ void sca_destroy(sca_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->dscalar) (void)hipFree(ctx->dscalar);
   delete ctx;
 }
 
@@ -414,8 +475,11 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
   if ((s = check_dev_ptr(ctx, m, "m"))) return s;
   if ((s = check_dev_ptr(ctx, v, "v"))) return s;
 
-  const int N = p->L * p->L, M = p->n_max, B = 2 * M;
+  const int N = p->L * p->L;
   int prec = route_of(p);
+  ProbDesc P = make_prob(p, phi, nullptr);
+  if ((s = plan_tail(ctx, p, phi, P))) return s;
+  int B = 2 * P.Me;
   Carve c;
   auto setup = [&]() -> sca_status {
     const size_t fb = factor_workspace_bytes(N, B, prec);
@@ -423,10 +487,10 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
     sca_status r = ensure_ws(ctx, c0.total);
     if (r) return r;
     c = carve((char*)ctx->ws, 1, N, B, prec, true, true, fb);
+    c.tail_on = P.Me < P.M;
     return SCA_OK;
   };
   if ((s = setup())) return s;
-  ProbDesc P = make_prob(p, phi, nullptr);
   P.m = m; P.v = v; P.phi_out = phi;
   P.lr = o->lr; P.beta1 = o->beta1; P.beta2 = o->beta2; P.eps = o->eps;
   P.adam_t = o->t0;
@@ -446,6 +510,17 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
         res->steps_done = done;
         res->flags |= SCA_FLAG_NONFINITE;
         return fail(SCA_ENUMERIC, "non-finite value at step %d", o->t0 + k);
+      }
+      if (S.tail_range) {
+        // the remaining steps factorise every frequency
+        res->flags |= SCA_FLAG_TAIL_RANGE;
+        P.Me = P.M;
+        P.tail_guard = 0.0;
+        B = 2 * P.M;
+        if ((s = setup())) return s;
+        P.adam_t = o->t0 + done;
+        P.steps_left = o->n_steps - done;
+        upload = true;
       }
       if (growth_exceeded(prec, S.pivot_growth)) {
         // the remaining steps run in FP64 where that path is built
@@ -476,6 +551,7 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
   }
   if (growth_exceeded(prec, S.pivot_growth))
     res->flags |= SCA_FLAG_PIVOT_GROWTH;
+  if (S.tail_range) res->flags |= SCA_FLAG_TAIL_RANGE;
   res->omega = S.omega;
   res->omega_tilde = S.omega_tilde;
   res->af_order = S.af_order;
@@ -569,6 +645,9 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
                          void* factors, double* omega2) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
+  if (p->tail != SCA_TAIL_NONE)
+    return fail(SCA_EUNSUPPORTED, "the factor buffer holds every frequency: "
+                "tail must be SCA_TAIL_NONE");
   DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
@@ -611,6 +690,9 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
                                  double* grad) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
+  if (p->tail != SCA_TAIL_NONE)
+    return fail(SCA_EUNSUPPORTED, "the factor buffer holds every frequency: "
+                "tail must be SCA_TAIL_NONE");
   DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
@@ -640,7 +722,7 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
   HIP_TRY(factor_backward(B, N, route_of(p), lay.lad, lay.dg, lay.fact, st));
   HIP_TRY(launch_reduce(c.probs, 1, N, lay.lad, lay.dg, lay.growth, c.stats,
-                        false, c.rws, st));
+                        false, c.rws, nullptr, nullptr, st));
   if (factor_backward_consumes(N, route_of(p))) {
     hh->state = kFactorsConsumed;
     HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice,

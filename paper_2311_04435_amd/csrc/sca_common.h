@@ -34,13 +34,25 @@ struct ProbDesc {
   int32_t hoff;          // h vectors: up at hoff, down at hoff + N
   int32_t adam_t;        // ADAM updates applied so far (next uses adam_t + 1)
   int32_t steps_left;    // updates still to apply; 0: evaluate only
-  int32_t pad_;
+  int32_t Me;            // frequencies factorised (n < Me); n in [Me, M) by
+                         // the moment expansion of the tail (Me == M: none)
+  double tail_guard;     // tail only: flag a pass whose Gershgorin bound on
+                         // the spectral radius of H exceeds this
 };
+
+// Matsubara tail by moments.  For w > rho(H),
+//   ln|det(i w - H)| = N ln w + 1/2 sum_{m>=1} (-1)^(m+1)/m tr(H^2m) / w^2m,
+//   Re[(i w - H)^-1]_ii = -sum_{m>=0} (-1)^m (H^(2m+1))_ii / w^(2m+2);
+// the series are cut after kTailK terms (powers of H up to kTailP).
+constexpr int kTailK = 14;
+constexpr int kTailP = 2 * kTailK + 1;
+constexpr int kTailS = kTailK + 2;   // sum of ln w_n, then S_2 .. S_{2K+2}
 
 // Per-problem statistics written by the reduction kernel.
 struct ProbStats {
   double omega, omega_tilde, max_abs_grad, af_order, pivot_growth;
-  int32_t nonfinite, pad_;
+  int32_t nonfinite;
+  int32_t tail_range;   // the tail's spectral bound exceeded its guard
 };
 
 // Number of lattice directions d in {+x,-x,+y,-y} with j = i + d (mod L).

@@ -212,7 +212,7 @@ hipError_t launch_reduce_omega(ProbDesc* probs, int nprob, int N,
                                const double* lad, const double* growth,
                                ProbStats* stats, void* ws, hipStream_t st) {
   return launch_reduce(probs, nprob, N, lad, nullptr, growth, stats, false, ws,
-                       st);
+                       nullptr, nullptr, st);
 }
 
 }  // namespace sca

@@ -37,6 +37,8 @@ ProbDesc make_prob(const sca_params* p, const double* phi, double* grad);
 struct Carve {
   ProbDesc* probs; MatDesc* descs; double* hbuf; double* lad; double* growth;
   double* dg; void* rws; ProbStats* stats; void* fact;
+  double* mom; double* tsum;   // Matsubara tail (moments, frequency sums)
+  bool tail_on;                // some problem of the batch has Me < M
   size_t total;
 };
 Carve carve(char* base, int nprob, int N, int B, int precision, bool own_dg,

@@ -10,8 +10,8 @@ namespace sca {
 hipError_t launch_hvec(const ProbDesc* probs, int nprob, int N, double* hbuf,
                        hipStream_t st);
 
-// Matsubara descriptors of every problem: for b in [mat_begin, +2M),
-// z = i w_n (n = (b - mat_begin) mod M), spin up for the first M.
+// Matsubara descriptors of every problem: for b in [mat_begin, +2 Me),
+// z = i w_n (n = (b - mat_begin) mod Me), spin up for the first Me.
 hipError_t launch_matsubara_descs(const ProbDesc* probs, int nprob,
                                   int max2M, MatDesc* descs, hipStream_t st);
 
@@ -29,12 +29,24 @@ hipError_t launch_small_factor(const MatDesc* descs, const double* hbuf, int B,
 // are only evaluated.  stats[p] receives Omega, Omega~, max|g|, |phi| (of
 // the phi the terms were evaluated at) and the largest pivot growth of the
 // problem's matrices.
+// Problems with Me < M add their tail from mom / tsum (launch_tail).
 hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
                          const double* dg, const double* growth,
                          ProbStats* stats, bool adam, void* ws,
+                         const double* mom, const double* tsum,
                          hipStream_t st);
 size_t reduce_workspace_bytes(int nprob);
 int reduce_max_sites();
+
+// Matsubara tail of every problem with Me < M: mom[p][s][q][i] =
+// (H_s^(q+1))_ii for q < kTailP, tsum[p] = (sum ln w_n, S_2, .., S_{2K+2})
+// over n in [Me, M).
+hipError_t launch_tail(const ProbDesc* probs, int nprob, int N,
+                       const double* hbuf, double* mom, double* tsum,
+                       hipStream_t st);
+size_t tail_workspace_bytes(int nprob, int N);
+// *out = max_i |x_i| (device scalar).
+hipError_t launch_absmax(const double* x, int n, double* out, hipStream_t st);
 
 // Descriptors for arbitrary shifts: b = s_idx * n_z + j, z = (z[2j], z[2j+1]),
 // h vector of spin s_idx at hoff0 + s_idx * N.

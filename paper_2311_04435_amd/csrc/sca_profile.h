@@ -20,6 +20,7 @@ enum KernelClass {
   K_TRTRI_SYM = 9,  // symmetric route: L^-T
   K_SYMDIAG = 10,   // symmetric route: diagonal of A^-1
   K_FALLBACK = 11,  // symmetric route: pivoted LU of flagged matrices
+  K_TAIL = 12,      // Matsubara tail: moments of H and frequency sums
   K_COUNT = 16
 };
 

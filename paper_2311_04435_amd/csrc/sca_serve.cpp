@@ -367,6 +367,9 @@ sca_status sca_server_submit(sca_server* s, const sca_params* p,
   sca_status st = validate_params(p);
   if (st) return st;
   if ((st = validate_adam_opts(o))) return st;
+  if (p->tail != SCA_TAIL_NONE)
+    return fail(SCA_EUNSUPPORTED, "the server factorises every frequency: "
+                "tail must be SCA_TAIL_NONE");
   if (o->grad_tol != 0.0 || o->check_every != 0)
     return fail(SCA_EINVAL, "grad_tol and check_every are not supported by "
                 "the server (requests run a fixed number of steps)");

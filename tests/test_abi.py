@@ -37,16 +37,18 @@ def test_library_exports_every_header_symbol():
 def _params(**kw):
     from paper_2311_04435_amd import _lib
     d = dict(L=4, n_max=256, precision=0, factor=0, t=1.0, U=4.0, delta=0.0,
-             T=0.1, onsite=None)
+             T=0.1, onsite=None, tail=0, reserved=0)
     d.update(kw)
     return _lib.Params(d["L"], d["n_max"], d["precision"], d["factor"], d["t"],
-                       d["U"], d["delta"], d["T"], d["onsite"])
+                       d["U"], d["delta"], d["T"], d["onsite"], d["tail"],
+                       d["reserved"])
 
 
 @pytest.mark.parametrize("bad", [dict(L=3), dict(L=0), dict(L=66), dict(n_max=0),
                                  dict(U=0.0), dict(U=-1.0), dict(T=0.0),
                                  dict(T=float("nan")), dict(t=float("inf")),
-                                 dict(precision=7), dict(factor=2)])
+                                 dict(precision=7), dict(factor=2),
+                                 dict(tail=2), dict(reserved=1)])
 def test_invalid_params_rejected_without_device(bad):
     from paper_2311_04435_amd import _lib
     p = _params(**bad)

@@ -1,0 +1,124 @@
+"""GPU parity of the Matsubara tail by moments (Params(tail=True)): only the
+frequencies below about 4x a spectral bound of H are factorised, the rest
+come from the moments of H.  The sums are the same, so the bar is the
+FP64 oracle's 1e-10 (Omega~, gradient, ADAM trajectory), on the 20x20
+Hubbard lattice at both temperatures, the 32x32 ionic lattice, a disordered
+lattice, and with the symmetric factorisation.  The tail kernels must run
+(profiled launches) and the guard must fire when phi outgrows the bound."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sca():
+    import torch
+    import paper_2311_04435_amd as sca
+    assert torch.cuda.is_available()
+    return sca
+
+
+def cuda(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+
+
+def pd(p):
+    return dict(L=p.L, t=p.t, U=p.U, delta=p.delta, T=p.T, n_max=p.n_max)
+
+
+def grad_err(g, gr, phi, U):
+    return float(np.max(np.abs(g - gr)) /
+                 max(np.max(np.abs(gr)), 2 * np.max(np.abs(phi)) / U))
+
+
+@pytest.mark.parametrize("name,factor", [("hubbard_20x20_T0.1", "lu"),
+                                         ("hubbard_20x20_T0.6", "lu"),
+                                         ("hubbard_20x20_T0.1", "ldlt"),
+                                         ("ionic_32x32_U4", "ldlt")])
+def test_tail_grad(sca, name, factor):
+    wl = synth.WORKLOADS[name]
+    p = sca.Params.from_dict(wl["params"], factor=factor, tail=True)
+    phi = synth.make_phi0(p.L, wl["phi0"])
+    ctx = sca.Context()
+    ctx.profile(True)
+    g, o2 = ctx.grad(p, cuda(phi))
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    assert prof["tail"][1] >= 1            # the moments ran
+    g, o2 = g.cpu().numpy(), o2.cpu().numpy()
+    om_t = oracle.omega_tilde(pd(p), phi)
+    gr = oracle.grad(pd(p), phi)
+    e_om = abs(o2[1] - om_t) / abs(om_t)
+    e_g = grad_err(g, gr, phi, p.U)
+    # Omega (not only Omega~): the N ln w_n of the tail frequencies
+    om_f = oracle.omega_full(pd(p), phi)
+    e_f = abs(o2[0] - om_f) / abs(om_f)
+    print(f"{name} {factor} tail: Omega~ {e_om:.1e} Omega {e_f:.1e} grad {e_g:.1e}")
+    assert e_om < 1e-10 and e_g < 1e-10 and e_f < 1e-10
+
+
+def test_tail_matches_full_gpu(sca):
+    """Tail and all-frequency evaluations on the GPU agree to rounding."""
+    wl = synth.WORKLOADS["hubbard_20x20_T0.6"]
+    phi = cuda(synth.make_phi0(20, wl["phi0"]))
+    g0, o0 = sca.grad(sca.Params.from_dict(wl["params"]), phi)
+    g1, o1 = sca.grad(sca.Params.from_dict(wl["params"], tail=True), phi)
+    e_g = float((g1 - g0).abs().max() / g0.abs().max())
+    e_o = float(((o1 - o0).abs() / o0.abs()).max())
+    print(f"tail vs all frequencies: grad {e_g:.1e} Omega {e_o:.1e}")
+    assert e_g < 1e-12 and e_o < 1e-11
+
+
+def test_tail_disordered(sca):
+    L = 12
+    eps = synth.uniform(1700, L * L, -1.0, 1.0)
+    phi = synth.uniform(1701, L * L, -0.5, 0.5)
+    p = sca.Params(L=L, U=3.0, T=0.15, n_max=256, delta=0.4,
+                   onsite=cuda(eps), tail=True)
+    g, o2 = sca.grad(p, cuda(phi))
+    om = oracle.omega_tilde(pd(p), phi, onsite=eps)
+    gr = oracle.grad(pd(p), phi, onsite=eps)
+    e_om = abs(o2[1].item() - om) / abs(om)
+    e_g = grad_err(g.cpu().numpy(), gr, phi, p.U)
+    print(f"disordered 12x12 tail: Omega~ {e_om:.1e} grad {e_g:.1e}")
+    assert e_om < 1e-10 and e_g < 1e-10
+
+
+def test_tail_trajectory_20x20(sca):
+    wl = synth.WORKLOADS["hubbard_20x20_T0.1"]
+    p = sca.Params.from_dict(wl["params"], factor="ldlt", tail=True)
+    phi0 = synth.make_phi0(20, wl["phi0"])
+    steps = 50
+    phi, m, v, res = sca.adam_solve(p, cuda(phi0), steps)
+    ref, info = oracle.adam_solve(pd(p), phi0, steps)
+    e = np.max(np.abs(phi.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    e_om = abs(res["omega_tilde"] - info["omega_tilde"]) / abs(info["omega_tilde"])
+    print(f"20x20 ldlt+tail {steps} steps: phi err {e:.2e} Omega~ err {e_om:.2e}")
+    assert e < 1e-10 and e_om < 1e-10
+    assert not (res["flags"] & sca.SCA_FLAG_TAIL_RANGE)
+
+
+def test_tail_guard_fires(sca):
+    """A learning rate that throws phi far outside the planned bound: the
+    pass that sees it sets the flag and the rest of the solve factorises
+    every frequency (results stay finite)."""
+    L = 8
+    p = sca.Params(L=L, U=0.5, T=0.1, n_max=256, tail=True)
+    phi0 = synth.uniform(1800, L * L, -0.1, 0.1)
+    phi, m, v, res = sca.adam_solve(p, cuda(phi0), 4, lr=8.0, check_every=1)
+    assert res["flags"] & sca.SCA_FLAG_TAIL_RANGE
+    assert np.all(np.isfinite(phi.cpu().numpy()))
+
+
+def test_tail_rejected_where_unsupported(sca):
+    from paper_2311_04435_amd import SCAError
+    from paper_2311_04435_amd.autograd import potential
+    p = sca.Params(L=8, U=4.0, T=0.1, n_max=64, tail=True)
+    phi = cuda(synth.uniform(1900, 64, -0.5, 0.5)).requires_grad_(True)
+    with pytest.raises(SCAError, match="UNSUPPORTED"):
+        potential(p, phi)
