@@ -96,10 +96,11 @@ typedef enum { SCA_FACTOR_LU = 0, SCA_FACTOR_LDLT = 1 } sca_factor;
  *                     SCA_FLAG_TAIL_RANGE (sca_potential and sca_grad then
  *                     re-evaluate without the tail; sca_adam_solve runs the
  *                     remaining steps without it from the check that saw
- *                     the flag).  The same sums are computed, only the
+ *                     the flag; the request server from the next chunk of
+ *                     passes).  The same sums are computed, only the
  *                     evaluation of the high frequencies differs.  Not
- *                     available for sca_factorize / sca_grad_from_factors or
- *                     the request server (SCA_EUNSUPPORTED). */
+ *                     available for sca_factorize / sca_grad_from_factors
+ *                     (SCA_EUNSUPPORTED). */
 typedef enum { SCA_TAIL_NONE = 0, SCA_TAIL_MOMENTS = 1 } sca_tail;
 
 /* One SCA problem.  onsite: optional DEVICE array of N extra site

@@ -41,9 +41,6 @@ sca_status fail(sca_status s, const char* fmt, ...) {
 
 #define HIP_TRY SCA_HIP_TRY
 
-namespace {
-constexpr double kPiHost = 3.14159265358979323846;
-}
 
 struct sca_ctx {
   int device = 0;
@@ -121,6 +118,22 @@ sca_status validate_adam_opts(const sca_adam_opts* o) {
       !(o->grad_tol >= 0.0))
     return fail(SCA_EINVAL, "invalid ADAM hyper-parameters");
   return SCA_OK;
+}
+
+void tail_split(const sca_params* p, double phi_max, double onsite_max,
+                ProbDesc& P) {
+  constexpr double kPi = 3.14159265358979323846;
+  P.Me = p->n_max;
+  P.tail_guard = 0.0;
+  if (p->tail != SCA_TAIL_MOMENTS) return;
+  const double phib = std::max(phi_max, 0.5 * p->U) + 0.5;
+  const double rho = 4.0 * std::fabs(p->t) + 0.5 * std::fabs(p->delta) +
+                     onsite_max + phib;
+  const double x = (4.0 * rho / (kPi * p->T) - 1.0) / 2.0;
+  const int me = x >= (double)p->n_max ? p->n_max
+                                       : std::max(1, (int)std::ceil(x));
+  P.Me = me;
+  P.tail_guard = (2.0 * me + 1.0) * kPi * p->T / 3.0;
 }
 
 ProbDesc make_prob(const sca_params* p, const double* phi, double* grad) {
@@ -220,12 +233,7 @@ sca_status plan_tail(sca_ctx* ctx, const sca_params* p, const double* phi,
   if (p->onsite && (s = device_absmax(ctx, p->onsite, N, &omax))) return s;
   if (!std::isfinite(pmax) || !std::isfinite(omax))
     return fail(SCA_ENUMERIC, "phi or onsite is not finite");
-  const double phib = std::max(pmax, 0.5 * p->U) + 0.5;
-  const double rho = 4.0 * std::fabs(p->t) + 0.5 * std::fabs(p->delta) + omax + phib;
-  const double x = (4.0 * rho / (kPiHost * p->T) - 1.0) / 2.0;
-  const int me = x >= (double)p->n_max ? p->n_max : std::max(1, (int)std::ceil(x));
-  P.Me = me;
-  P.tail_guard = (2.0 * me + 1.0) * kPiHost * p->T / 3.0;
+  tail_split(p, pmax, omax, P);
   return SCA_OK;
 }
 

@@ -29,8 +29,15 @@ sca_status validate_adam_opts(const sca_adam_opts* o);
 sca_status check_device_ptr(int device, const void* ptr, const char* name,
                             bool allow_null);
 
-// Problem descriptor of one parameter point (no ADAM state, offsets 0).
+// Problem descriptor of one parameter point (no ADAM state, offsets 0;
+// every frequency factorised).
 ProbDesc make_prob(const sca_params* p, const double* phi, double* grad);
+
+// SCA_TAIL_MOMENTS split of a parameter point, from max|phi| and
+// max|onsite|: P.Me = the frequencies factorised, P.tail_guard = the
+// spectral bound above which a pass is flagged (see include/sca.h).
+void tail_split(const sca_params* p, double phi_max, double onsite_max,
+                ProbDesc& P);
 
 // Workspace carve-up for one batch of `nprob` problems of N sites with B
 // matrices in total (base == nullptr: sizes only, in `total`).

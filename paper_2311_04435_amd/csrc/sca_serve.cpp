@@ -62,6 +62,8 @@ struct Request {
   double* phi = nullptr;
   double* m = nullptr;
   double* v = nullptr;
+  int Me = 0;              // frequencies factorised (tail: < n_max)
+  double tail_guard = 0.0;
   int passes_total = 0;   // ADAM passes + the final evaluation (if any)
   int passes_enq = 0;     // passes enqueued so far
   Group* group = nullptr;
@@ -117,6 +119,7 @@ struct sca_server {
   std::deque<Request*> queue;
   std::vector<std::unique_ptr<Group>> groups;
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
+  double* dscalar = nullptr;   // device scratch of the tail planning
   bool broken = false;
 
   double now() const {
@@ -222,8 +225,12 @@ sca_status admit(sca_server* s) {
 // Enqueue the next chunk of passes of an idle group with members.
 sca_status launch(sca_server* s, Group* g) {
   const int n = (int)g->mem.size();
-  const int B = 2 * g->M * n;
+  int B = 0, max2M = 0;
+  for (const Request* r : g->mem) { B += 2 * r->Me; max2M = std::max(max2M, 2 * r->Me); }
+  g->c.tail_on = false;
+  for (const Request* r : g->mem) g->c.tail_on |= r->Me < r->p.n_max;
   if (g->dirty) {
+    int mb = 0;   // members' matrices side by side
     for (int k = 0; k < n; ++k) {
       const Request* r = g->mem[k];
       ProbDesc P = make_prob(&r->p, r->phi, nullptr);
@@ -233,14 +240,17 @@ sca_status launch(sca_server* s, Group* g) {
       const int applied = std::min(r->passes_enq, r->o.n_steps);
       P.adam_t = r->o.t0 + applied;
       P.steps_left = r->o.n_steps - applied;
-      P.mat_begin = 2 * g->M * k;
+      P.Me = r->Me;
+      P.tail_guard = r->tail_guard;
+      P.mat_begin = mb;
+      mb += 2 * r->Me;
       P.hoff = 2 * g->N * k;
       g->pin_probs[k] = P;
     }
     // the group is idle: no copy from pin_probs is pending
     SCA_HIP_TRY(hipMemcpyAsync(g->c.probs, g->pin_probs, sizeof(ProbDesc) * n,
                                hipMemcpyHostToDevice, g->st));
-    SCA_HIP_TRY(launch_matsubara_descs(g->c.probs, n, 2 * g->M, g->c.descs,
+    SCA_HIP_TRY(launch_matsubara_descs(g->c.probs, n, max2M, g->c.descs,
                                        g->st));
     g->dirty = false;
   }
@@ -271,15 +281,24 @@ void complete(sca_server* s, Group* g) {
   std::vector<Request*> keep;
   for (size_t k = 0; k < g->mem.size(); ++k) {
     Request* r = g->mem[k];
-    if (r->passes_enq < r->passes_total) { keep.push_back(r); continue; }
     const ProbStats& S = g->pin_stats[k];
+    if (S.tail_range && r->Me < r->p.n_max) {
+      // the spectral bound left the tail's range: the following passes
+      // factorise every frequency
+      r->res.flags |= SCA_FLAG_TAIL_RANGE;
+      r->Me = r->p.n_max;
+      r->tail_guard = 0.0;
+      g->dirty = true;
+    }
+    if (r->passes_enq < r->passes_total) { keep.push_back(r); continue; }
     r->res.omega = S.omega;
     r->res.omega_tilde = S.omega_tilde;
     r->res.af_order = S.af_order;
     r->res.max_abs_grad = S.max_abs_grad;
     r->res.max_pivot_growth = S.pivot_growth;
     r->res.steps_done = r->o.n_steps;
-    r->res.flags = 0;
+    r->res.flags &= SCA_FLAG_TAIL_RANGE;
+    if (S.tail_range) r->res.flags |= SCA_FLAG_TAIL_RANGE;
     if (S.nonfinite) r->res.flags |= SCA_FLAG_NONFINITE;
     if ((route_of(&r->p) & kModeFp32) && !(S.pivot_growth <= 1e3))
       r->res.flags |= SCA_FLAG_PIVOT_GROWTH;
@@ -354,6 +373,7 @@ void sca_server_destroy(sca_server* s) {
   if (!s) return;
   DevScope d(s->device);
   s->groups.clear();
+  if (s->dscalar) (void)hipFree(s->dscalar);
   delete s;
 }
 
@@ -367,9 +387,6 @@ sca_status sca_server_submit(sca_server* s, const sca_params* p,
   sca_status st = validate_params(p);
   if (st) return st;
   if ((st = validate_adam_opts(o))) return st;
-  if (p->tail != SCA_TAIL_NONE)
-    return fail(SCA_EUNSUPPORTED, "the server factorises every frequency: "
-                "tail must be SCA_TAIL_NONE");
   if (o->grad_tol != 0.0 || o->check_every != 0)
     return fail(SCA_EINVAL, "grad_tol and check_every are not supported by "
                 "the server (requests run a fixed number of steps)");
@@ -383,6 +400,26 @@ sca_status sca_server_submit(sca_server* s, const sca_params* p,
     return fail(SCA_ENOMEM, "a request of L=%d needs %zu bytes, above the "
                 "server budget of %zu", p->L, one, s->budget);
   auto r = std::make_unique<Request>();
+  r->Me = p->n_max;
+  if (p->tail == SCA_TAIL_MOMENTS) {
+    // max|phi| (and max|onsite|) of the starting point; phi is ready (the
+    // caller's contract), read on the null stream
+    DevScope d(s->device);
+    if (!s->dscalar) SCA_HIP_TRY(hipMalloc(&s->dscalar, sizeof(double)));
+    double pm = 0.0, om = 0.0;
+    SCA_HIP_TRY(launch_absmax(phi, p->L * p->L, s->dscalar, nullptr));
+    SCA_HIP_TRY(hipMemcpy(&pm, s->dscalar, sizeof pm, hipMemcpyDeviceToHost));
+    if (p->onsite) {
+      SCA_HIP_TRY(launch_absmax(p->onsite, p->L * p->L, s->dscalar, nullptr));
+      SCA_HIP_TRY(hipMemcpy(&om, s->dscalar, sizeof om, hipMemcpyDeviceToHost));
+    }
+    if (!std::isfinite(pm) || !std::isfinite(om))
+      return fail(SCA_ENUMERIC, "phi or onsite is not finite");
+    ProbDesc P{};
+    tail_split(p, pm, om, P);
+    r->Me = P.Me;
+    r->tail_guard = P.tail_guard;
+  }
   r->id = s->next_id++;
   r->p = *p;
   r->o = *o;

@@ -72,7 +72,7 @@ def staggered_start(L: int, seed: int, m0: float = 1.0,
 def run(pts: List[dict], steps: int = 1000, factor: str = "ldlt",
         precision: str = "fp64", lr: float = 0.01, m0: float = 1.0,
         server: Optional[Server] = None, max_batch: int = 16,
-        progress: bool = False) -> List[dict]:
+        progress: bool = False, tail: bool = False) -> List[dict]:
     """Solve every point (through one server); returns per point the
     parameters, |phi|, Omega~, max|g|, and phi itself (float64 CPU array)."""
     own = server is None
@@ -82,7 +82,7 @@ def run(pts: List[dict], steps: int = 1000, factor: str = "ldlt",
         for k, pt in enumerate(pts):
             p = Params(L=pt["L"], U=pt["U"], T=pt["T"], n_max=pt["n_max"],
                        delta=pt.get("delta", 0.0), t=pt.get("t", 1.0),
-                       precision=precision, factor=factor)
+                       precision=precision, factor=factor, tail=tail)
             phi0 = torch.as_tensor(staggered_start(pt["L"], 4000 + k, m0),
                                    dtype=torch.float64, device="cuda")
             tickets.append((srv.submit(p, phi0, steps, lr=lr), p))
@@ -127,10 +127,13 @@ def main(argv=None):
     ap.add_argument("--L", type=int, default=20)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--factor", default="ldlt")
+    ap.add_argument("--tail", action="store_true",
+                    help="high Matsubara frequencies from the moments of H")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     pts = points(args.experiment, args.L)
-    res = run(pts, args.steps, factor=args.factor, progress=True)
+    res = run(pts, args.steps, factor=args.factor, progress=True,
+              tail=args.tail)
     rows: List[Dict] = []
     w = np.linspace(-6.0, 6.0, 241)
     for r in res:

@@ -117,3 +117,25 @@ def test_server_argument_errors(sca):
     with Server(hbm_budget_bytes=1024) as srv:
         with pytest.raises(SCAError, match="ENOMEM"):
             srv.submit(p, cuda(np.zeros(16)), 3)
+
+
+def test_tail_requests_bitwise(sca):
+    """Requests with the Matsubara tail (fewer matrices each) share groups
+    with ordinary ones of the same shape; each still matches its own
+    sca.adam_solve bit for bit."""
+    from paper_2311_04435_amd.serve import Server
+    reqs = []
+    for k in range(6):
+        r = synth.uniform(1200 + k, 3, 0.0, 1.0)
+        p = sca.Params(L=12, U=3.0 + 2.0 * r[0], delta=r[1], T=0.1 + 0.1 * r[2],
+                       n_max=128, factor="ldlt" if k % 3 == 2 else "lu",
+                       tail=(k % 2 == 0))
+        reqs.append(dict(params=p, phi0=cuda(synth.uniform(40 + k, 144, -0.5, 0.5)),
+                         n_steps=6 + k, lr=0.02, final_eval=True))
+    with Server(max_batch=4) as srv:
+        tickets = [srv.submit(r["params"], r["phi0"], r["n_steps"], lr=r["lr"])
+                   for r in reqs]
+        done = srv.drain(tickets)
+    for t in tickets:
+        assert not (done[t][3]["flags"] & sca.SCA_FLAG_TAIL_RANGE)
+    check_same(sca, reqs, [done[t] for t in tickets])
