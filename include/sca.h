@@ -98,9 +98,9 @@ typedef enum { SCA_FACTOR_LU = 0, SCA_FACTOR_LDLT = 1 } sca_factor;
  *                     remaining steps without it from the check that saw
  *                     the flag; the request server from the next chunk of
  *                     passes).  The same sums are computed, only the
- *                     evaluation of the high frequencies differs.  Not
- *                     available for sca_factorize / sca_grad_from_factors
- *                     (SCA_EUNSUPPORTED). */
+ *                     evaluation of the high frequencies differs.
+ *                     sca_factorize keeps the split it chose in the factor
+ *                     buffer and sca_grad_from_factors uses it. */
 typedef enum { SCA_TAIL_NONE = 0, SCA_TAIL_MOMENTS = 1 } sca_tail;
 
 /* One SCA problem.  onsite: optional DEVICE array of N extra site

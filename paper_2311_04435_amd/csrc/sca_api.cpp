@@ -653,35 +653,38 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
                          void* factors, double* omega2) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
-  if (p->tail != SCA_TAIL_NONE)
-    return fail(SCA_EUNSUPPORTED, "the factor buffer holds every frequency: "
-                "tail must be SCA_TAIL_NONE");
   DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
   if ((s = check_dev_ptr(ctx, omega2, "omega2"))) return s;
-  const int N = p->L * p->L, M = p->n_max, B = 2 * M;
-  Carve c0 = carve(nullptr, 1, N, B, route_of(p), false, false, 0);
+  const int N = p->L * p->L, B = 2 * p->n_max;
+  ProbDesc P = make_prob(p, phi, nullptr);
+  if ((s = plan_tail(ctx, p, phi, P))) return s;
+  const int Be = 2 * P.Me;   // matrices factorised (the layout holds B)
+  Carve c0 = carve(nullptr, 1, N, Be, route_of(p), false, false, 0);
   if ((s = ensure_ws(ctx, c0.total))) return s;
-  Carve c = carve((char*)ctx->ws, 1, N, B, route_of(p), false, false, 0);
+  Carve c = carve((char*)ctx->ws, 1, N, Be, route_of(p), false, false, 0);
   AutogradLayout lay = autograd_layout(factors, N, B, route_of(p));
   c.lad = lay.lad;
   c.dg = lay.dg;
   c.fact = lay.fact;
-  ProbDesc P = make_prob(p, phi, nullptr);
+  c.tail_on = P.Me < P.M;
   hipStream_t st = ctx->stream;
   if ((s = ensure_pinned(ctx, 512))) return s;
   HIP_TRY(hipStreamSynchronize(st));
   std::memcpy(ctx->pinned, &P, sizeof P);
   FactorHeader* hh = reinterpret_cast<FactorHeader*>(
       static_cast<char*>(ctx->pinned) + 256);
-  *hh = FactorHeader{kFactorsReady, p->L, p->n_max, route_of(p)};
+  *hh = FactorHeader{kFactorsReady, p->L, p->n_max, route_of(p), p->tail,
+                     P.Me, P.tail_guard};
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_matsubara_descs(c.probs, 1, B, c.descs, st));
+  HIP_TRY(launch_matsubara_descs(c.probs, 1, Be, c.descs, st));
   HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
-  HIP_TRY(factor_forward(c.descs, c.hbuf, B, N, p->L, route_of(p), c.lad,
+  if (c.tail_on) HIP_TRY(launch_tail(c.probs, 1, N, c.hbuf, c.mom, c.tsum, st));
+  HIP_TRY(factor_forward(c.descs, c.hbuf, Be, N, p->L, route_of(p), c.lad,
                          c.dg, c.growth, c.fact, st));
-  HIP_TRY(launch_reduce_omega(c.probs, 1, N, c.lad, c.growth, c.stats, c.rws, st));
+  HIP_TRY(launch_reduce_omega(c.probs, 1, N, c.lad, c.growth, c.stats, c.rws,
+                              c.mom, c.tsum, st));
   HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice, st));
   ProbStats S;
   if ((s = read_stats(ctx, c, 1, &S))) return s;
@@ -698,17 +701,11 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
                                  double* grad) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
-  if (p->tail != SCA_TAIL_NONE)
-    return fail(SCA_EUNSUPPORTED, "the factor buffer holds every frequency: "
-                "tail must be SCA_TAIL_NONE");
   DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
   if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
-  const int N = p->L * p->L, M = p->n_max, B = 2 * M;
-  Carve c0 = carve(nullptr, 1, N, B, route_of(p), false, false, 0);
-  if ((s = ensure_ws(ctx, c0.total))) return s;
-  Carve c = carve((char*)ctx->ws, 1, N, B, route_of(p), false, false, 0);
+  const int N = p->L * p->L, B = 2 * p->n_max;
   AutogradLayout lay = autograd_layout(factors, N, B, route_of(p));
   ProbDesc P = make_prob(p, phi, grad);
   hipStream_t st = ctx->stream;
@@ -723,14 +720,27 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
                 "sca_grad_from_factors (this path inverts them in place); "
                 "call sca_factorize again");
   if (hh->state != kFactorsReady || hh->L != p->L || hh->n_max != p->n_max ||
-      hh->mode != route_of(p))
+      hh->mode != route_of(p) || hh->tail != p->tail || hh->Me < 1 ||
+      hh->Me > p->n_max)
     return fail(SCA_EINVAL, "factors do not hold a factorisation of these "
                 "params (sca_factorize not called with them)");
+  // the frequencies the forward factorised; the tail again from phi
+  P.Me = hh->Me;
+  P.tail_guard = hh->tail_guard;
+  const int Be = 2 * P.Me;
+  Carve c0 = carve(nullptr, 1, N, Be, route_of(p), false, false, 0);
+  if ((s = ensure_ws(ctx, c0.total))) return s;
+  Carve c = carve((char*)ctx->ws, 1, N, Be, route_of(p), false, false, 0);
+  c.tail_on = P.Me < P.M;
   std::memcpy(ctx->pinned, &P, sizeof P);
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
-  HIP_TRY(factor_backward(B, N, route_of(p), lay.lad, lay.dg, lay.fact, st));
+  if (c.tail_on) {
+    HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
+    HIP_TRY(launch_tail(c.probs, 1, N, c.hbuf, c.mom, c.tsum, st));
+  }
+  HIP_TRY(factor_backward(Be, N, route_of(p), lay.lad, lay.dg, lay.fact, st));
   HIP_TRY(launch_reduce(c.probs, 1, N, lay.lad, lay.dg, lay.growth, c.stats,
-                        false, c.rws, nullptr, nullptr, st));
+                        false, c.rws, c.mom, c.tsum, st));
   if (factor_backward_consumes(N, route_of(p))) {
     hh->state = kFactorsConsumed;
     HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice,

@@ -210,9 +210,10 @@ hipError_t launch_make_shifts(const double* w, int n_w, double eta, double* z,
 
 hipError_t launch_reduce_omega(ProbDesc* probs, int nprob, int N,
                                const double* lad, const double* growth,
-                               ProbStats* stats, void* ws, hipStream_t st) {
+                               ProbStats* stats, void* ws, const double* mom,
+                               const double* tsum, hipStream_t st) {
   return launch_reduce(probs, nprob, N, lad, nullptr, growth, stats, false, ws,
-                       nullptr, nullptr, st);
+                       mom, tsum, st);
 }
 
 }  // namespace sca

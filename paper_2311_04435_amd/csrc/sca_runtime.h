@@ -36,7 +36,11 @@ hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
 // what the backward needs; the backward completes dg from it.  The buffer
 // starts with a header naming the problem shape and whether the factors are
 // still usable: the FP64 blocked backward inverts them in place.
-struct FactorHeader { uint32_t state; int32_t L, n_max, mode; };
+struct FactorHeader {
+  uint32_t state; int32_t L, n_max, mode;
+  int32_t tail, Me;    // tail option and frequencies factorised (n < Me)
+  double tail_guard;
+};
 constexpr uint32_t kFactorsReady = 0x5CA10001u;
 constexpr uint32_t kFactorsConsumed = 0x5CA10002u;
 struct AutogradLayout {
@@ -55,7 +59,8 @@ hipError_t factor_backward(int B, int N, int mode, const double* lad,
 // Omega, Omega~ of every problem without the gradient (dg not read).
 hipError_t launch_reduce_omega(ProbDesc* probs, int nprob, int N,
                                const double* lad, const double* growth,
-                               ProbStats* stats, void* ws, hipStream_t st);
+                               ProbStats* stats, void* ws, const double* mom,
+                               const double* tsum, hipStream_t st);
 
 // z[2j] = w[j], z[2j+1] = eta.
 hipError_t launch_make_shifts(const double* w, int n_w, double eta, double* z,

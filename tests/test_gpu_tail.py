@@ -4,7 +4,8 @@ come from the moments of H.  The sums are the same, so the bar is the
 FP64 oracle's 1e-10 (Omega~, gradient, ADAM trajectory), on the 20x20
 Hubbard lattice at both temperatures, the 32x32 ionic lattice, a disordered
 lattice, and with the symmetric factorisation.  The tail kernels must run
-(profiled launches) and the guard must fire when phi outgrows the bound."""
+(profiled launches), the guard must fire when phi outgrows the bound, and
+the autograd form must agree with sca.grad bit for bit."""
 import numpy as np
 import pytest
 
@@ -115,10 +116,17 @@ def test_tail_guard_fires(sca):
     assert np.all(np.isfinite(phi.cpu().numpy()))
 
 
-def test_tail_rejected_where_unsupported(sca):
-    from paper_2311_04435_amd import SCAError
+def test_tail_autograd(sca):
+    """The differentiable form with the tail: forward and backward give
+    exactly what sca.grad gives with the same params."""
+    import torch
     from paper_2311_04435_amd.autograd import potential
-    p = sca.Params(L=8, U=4.0, T=0.1, n_max=64, tail=True)
-    phi = cuda(synth.uniform(1900, 64, -0.5, 0.5)).requires_grad_(True)
-    with pytest.raises(SCAError, match="UNSUPPORTED"):
-        potential(p, phi)
+    for factor in ("lu", "ldlt"):
+        p = sca.Params(L=12, U=4.0, T=0.1, n_max=128, delta=0.5,
+                       factor=factor, tail=True)
+        phi = cuda(synth.uniform(1900, 144, -0.5, 0.5)).requires_grad_(True)
+        o2 = potential(p, phi)
+        o2[1].backward()
+        g_ref, o_ref = sca.grad(p, phi.detach())
+        assert torch.equal(o2.detach(), o_ref), factor
+        assert torch.equal(phi.grad, g_ref), factor
