@@ -19,6 +19,9 @@ Prints one JSON line.  Besides the contract fields it carries
   symmetric_ldlt the same workload on the symmetric route (unpivoted
                 L D L^T, exact for these complex symmetric matrices, half
                 the flops) with its own roofline;
+  hmc           Hybrid Monte Carlo of exp(-Omega/T) on the workload
+                (symmetric route with the tail): trajectories/s,
+                acceptance;
   tail          the same workload with only the low Matsubara frequencies
                 factorised and the rest from the moments of H (pivoted LU,
                 then symmetric), with n_factorised and their rooflines;
@@ -93,6 +96,36 @@ def kernel_work(kind: str, N: int, B: int):
     if kind == "reduce":      # reads diag(A^-1) of every matrix
         return B * 16.0 * N, "byte", "hbm"
     return None
+
+
+def hmc_line(sca, name, n_traj=4, n_leap=10, eps=0.02, factor="ldlt",
+             tail=True):
+    """Hybrid Monte Carlo of exp(-Omega/T) on a workload: trajectories/s
+    (n_leap + 1 force evaluations each) from the converged antiferromagnet
+    neighbourhood (staggered start), momenta and uniforms seeded."""
+    import torch
+    import synth
+    wl = synth.WORKLOADS[name]
+    p = sca.Params.from_dict(wl["params"], factor=factor, tail=tail)
+    N = p.L * p.L
+    phi = torch.as_tensor(synth.phi0_staggered(p.L, 7, 1.0, 0.05),
+                          dtype=torch.float64).cuda()
+    moms = torch.as_tensor(synth.normal(8, (n_traj + 1) * N).reshape(
+        n_traj + 1, N), dtype=torch.float64).cuda()
+    us = synth.uniform(9, n_traj + 1, 0.0, 1.0)
+    ctx = sca.Context()
+    ctx.hmc(p, phi, moms[:1], us[:1], eps, n_leap)      # warm-up trajectory
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc, h0, h1 = ctx.hmc(p, phi, moms[1:], us[1:], eps, n_leap)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": name, "factor": factor, "tail": tail,
+            "n_leap": n_leap, "eps": eps, "trajectories": n_traj,
+            "trajectories_per_s": n_traj / dt,
+            "force_evals_per_s": n_traj * (n_leap + 1) / dt,
+            "acceptance": float(acc.mean()),
+            "mean_abs_dH": float(abs(h1 - h0).mean())}
 
 
 def cpu_baseline(wl, budget_s: float):
@@ -285,6 +318,8 @@ def main():
     ap.add_argument("--no-l32", action="store_true")
     ap.add_argument("--no-tail", action="store_true",
                     help="skip the Matsubara-tail lines")
+    ap.add_argument("--no-hmc", action="store_true",
+                    help="skip the Hybrid Monte Carlo line")
     ap.add_argument("--no-symmetric", action="store_true",
                     help="skip the symmetric-route line")
     ap.add_argument("--serving-requests", type=int, default=32,
@@ -414,6 +449,8 @@ def main():
         out["tail"] = [route_line(sca, args.workload, "fp64", f,
                                   max(args.steps, 20), args.warmup, tail=True)
                        for f in ("lu", "ldlt")]
+    if prec == "fp64" and not args.no_hmc:
+        out["hmc"] = hmc_line(sca, args.workload)
     if args.serving_requests > 0:
         Ls = tuple(int(x) for x in args.serving_L.split(","))
         out["serving"] = serving(sca, args.serving_requests, args.serving_steps,

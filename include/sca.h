@@ -177,6 +177,30 @@ SCA_API sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
                           const sca_adam_opts* opts, double* phi, double* m,
                           double* v, sca_result* res);
 
+/* Hybrid Monte Carlo sampling of the static-field weight exp(-Omega(phi)/T)
+ * (the SCA partition function, Z = integral over phi of exp(-Omega/T),
+ * Sec. II; Omega~ is used, which differs by a constant).  Trajectory t
+ * starts from the current phi with momentum momenta[t][N] (device; the
+ * caller draws it, normally standard normal), takes n_leap leapfrog steps
+ * of size eps in H = Omega~/T + |p|^2/2 (every force evaluation is a full
+ * pass over the Matsubara matrices on the device; the kick and drift are
+ * fused into its reduction) and is accepted if
+ * uniforms[t] < exp(-(H_new - H_old)) (uniforms: host array, the caller's
+ * draws in [0, 1)); on rejection phi returns to the trajectory's start.
+ * Outputs on the host: accepted[t] (0/1), h_old[t], h_new[t].  phi (device,
+ * in/out) ends at the chain's last state.  With SCA_TAIL_MOMENTS a
+ * trajectory whose end points leave the tail's range returns
+ * SCA_ENUMERIC. */
+typedef struct {
+  double eps;       /* leapfrog step, > 0 */
+  int32_t n_leap;   /* leapfrog steps per trajectory, >= 1 */
+  int32_t n_traj;   /* trajectories, >= 0 */
+} sca_hmc_opts;
+SCA_API sca_status sca_hmc(sca_ctx* ctx, const sca_params* p,
+                           const sca_hmc_opts* opts, double* phi,
+                           const double* momenta, const double* uniforms,
+                           int32_t* accepted, double* h_old, double* h_new);
+
 /* Density of states per spin (Eq. (8), mu = 0): rho[2][n_w] (spin up first)
  * at the n_w real frequencies w[n_w], broadening eta > 0. */
 SCA_API sca_status sca_dos(sca_ctx* ctx, const sca_params* p, const double* phi,

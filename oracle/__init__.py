@@ -25,7 +25,8 @@ Two routes that share no code:
                           for 4x4 matrices.
   route S (`spectral`) -- eigendecomposition of H_s and the Matsubara sums.
 `closed` holds the Bloch closed forms for a staggered field, the infinite-M
-limits and the Hartree-Fock equation; `adam` the Kingma-Ba recurrence.
+limits and the Hartree-Fock equation; `adam` the Kingma-Ba recurrence;
+`hmc` Hybrid Monte Carlo of the static-field weight exp(-Omega/T).
 
 Parity status per function is listed in each module's docstring; every
 function here is pinned by a test under tests/ that does not re-type its
@@ -40,6 +41,7 @@ from .spectral import (omega_spectral, grad_spectral, dos_spectral,
 from .api import (omega_tilde, omega_full, grad, af_order, dos, adam_solve,
                   shifted_terms, shifted_terms_s, omega_tilde_d, grad_d)
 from .adam import AdamState, adam_step
+from .hmc import hmc_hamiltonian, leapfrog, hmc_chain
 
 __all__ = [
     "neighbours", "kinetic_matrix", "stagger_signs", "hamiltonian",
@@ -48,5 +50,6 @@ __all__ = [
     "grad_spectral", "dos_spectral", "terms_spectral", "omega_tilde",
     "omega_full", "grad", "af_order", "dos", "adam_solve", "shifted_terms",
     "shifted_terms_s",
-    "omega_tilde_d", "grad_d", "AdamState", "adam_step",
+    "omega_tilde_d", "grad_d", "AdamState", "adam_step", "hmc_hamiltonian",
+    "leapfrog", "hmc_chain",
 ]

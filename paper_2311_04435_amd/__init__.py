@@ -147,6 +147,32 @@ class Context:
             _dev(v, p.N, "v").data_ptr(), C.byref(res)))
         return {f: getattr(res, f) for f, _ in _lib.Result._fields_}
 
+    def hmc(self, p: Params, phi: torch.Tensor, momenta: torch.Tensor,
+            uniforms, eps: float, n_leap: int):
+        """Hybrid Monte Carlo chain in place on phi: trajectory t starts with
+        momentum momenta[t] (float64 CUDA [n_traj, N]) and is accepted if
+        uniforms[t] < exp(-dH).  Returns (accepted, h_old, h_new) as NumPy
+        arrays."""
+        import numpy as np
+        n_traj = 0 if momenta is None else momenta.shape[0]
+        if n_traj:
+            _dev(momenta.reshape(-1), n_traj * p.N, "momenta")
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        if u.shape != (n_traj,):
+            raise ValueError("uniforms must hold one draw per trajectory")
+        acc = np.zeros(n_traj, dtype=np.int32)
+        h0 = np.zeros(n_traj)
+        h1 = np.zeros(n_traj)
+        opts = _lib.HmcOpts(eps, n_leap, n_traj)
+        dbl = C.POINTER(C.c_double)
+        _lib.check(_lib.lib.sca_hmc(
+            self._h, C.byref(p.c()), C.byref(opts),
+            _dev(phi, p.N, "phi").data_ptr(),
+            momenta.data_ptr() if n_traj else None,
+            u.ctypes.data_as(dbl), acc.ctypes.data_as(C.POINTER(C.c_int32)),
+            h0.ctypes.data_as(dbl), h1.ctypes.data_as(dbl)))
+        return acc, h0, h1
+
     def dos(self, p: Params, phi: torch.Tensor, w: torch.Tensor, eta: float):
         w = _dev(w, None, "w")
         rho = self._empty(2, w.numel())
@@ -249,6 +275,15 @@ def tail_split(p: Params, phi: torch.Tensor) -> int:
     rho = 4 * abs(p.t) + 0.5 * abs(p.delta) + omax + max(pmax, 0.5 * p.U) + 0.5
     x = (4 * rho / (math.pi * p.T) - 1) / 2
     return p.n_max if x >= p.n_max else max(1, math.ceil(x))
+
+
+def hmc(p: Params, phi0: torch.Tensor, momenta: torch.Tensor, uniforms,
+        eps: float, n_leap: int):
+    """HMC chain from phi0 (not modified); returns (phi, accepted, h_old,
+    h_new)."""
+    phi = phi0.clone()
+    acc, h0, h1 = default_context().hmc(p, phi, momenta, uniforms, eps, n_leap)
+    return phi, acc, h0, h1
 
 
 def dos(p: Params, phi: torch.Tensor, w: torch.Tensor, eta: float = 0.05):

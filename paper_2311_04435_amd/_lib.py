@@ -28,7 +28,8 @@ KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
 
 # Every symbol include/sca.h declares.
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",
-           "sca_grad", "sca_adam_solve", "sca_dos", "sca_shifted_terms",
+           "sca_grad", "sca_adam_solve", "sca_hmc", "sca_dos",
+           "sca_shifted_terms",
            "sca_factor_bytes", "sca_factorize", "sca_grad_from_factors",
            "sca_profile", "sca_profile_read", "sca_server_create",
            "sca_server_destroy", "sca_server_clock", "sca_server_submit",
@@ -41,6 +42,11 @@ class Params(C.Structure):
                 ("t", C.c_double), ("U", C.c_double), ("delta", C.c_double),
                 ("T", C.c_double), ("onsite", C.c_void_p),
                 ("tail", C.c_int32), ("reserved", C.c_int32)]
+
+
+class HmcOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("n_leap", C.c_int32),
+                ("n_traj", C.c_int32)]
 
 
 class AdamOpts(C.Structure):
@@ -79,6 +85,9 @@ def _load():
         "sca_potential": (i32, [vp, P, dp, dp]),
         "sca_grad": (i32, [vp, P, dp, dp, dp]),
         "sca_adam_solve": (i32, [vp, P, O, dp, dp, dp, R]),
+        "sca_hmc": (i32, [vp, P, C.POINTER(HmcOpts), dp, dp,
+                          C.POINTER(C.c_double), C.POINTER(i32),
+                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "sca_dos": (i32, [vp, P, dp, dp, i32, C.c_double, dp]),
         "sca_shifted_terms": (i32, [vp, P, dp, dp, i32, dp, dp]),
         "sca_factor_bytes": (C.c_size_t, [P]),

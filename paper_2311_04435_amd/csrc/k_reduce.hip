@@ -78,6 +78,7 @@ struct ChunkPartial {
   double stag;      // sum (-1)^(x+y) phi_i
   double gmax;      // max |g_i|
   double hmax;      // max_i max_s |h_i| (Gershgorin bound of the tail guard)
+  double kin0, kin; // HMC: sum p^2 before / after the kick
   int32_t nonfinite, pad_;
 };
 
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(kReduceThreads)
 site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
                    const double* __restrict__ dg, ChunkPartial* __restrict__ part,
                    int adam, const double* __restrict__ mom,
-                   const double* __restrict__ tsum) {
+                   const double* __restrict__ tsum, int hmc) {
   const int p = blockIdx.y;
   const int chunk = blockIdx.x;
   const ProbDesc P = probs[p];
@@ -94,7 +95,7 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
   const int bpart = tid / kSitesPerBlock;
   const int i = chunk * kSitesPerBlock + site_l;
   __shared__ double acc_s[kBParts][kSitesPerBlock];
-  __shared__ double red_s[4][kSitesPerBlock];
+  __shared__ double red_s[6][kSitesPerBlock];
   __shared__ int nf_s[kSitesPerBlock];
 
   // sum over the problem's 2 Me matrices, split in kBParts contiguous ranges
@@ -114,7 +115,7 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
   acc_s[bpart][site_l] = acc;
   __syncthreads();
   if (bpart == 0) {
-    double phi2 = 0.0, stag = 0.0, ga = 0.0, hm = 0.0;
+    double phi2 = 0.0, stag = 0.0, ga = 0.0, hm = 0.0, k0 = 0.0, k1 = 0.0;
     int nf = 0;
     if (i < N) {
       double s = acc_s[0][site_l];
@@ -145,6 +146,22 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
       stag = (double)stagger_sign(i, P.L) * ph;
       ga = fabs(g);
       nf = !isfinite(g);
+      if (hmc && dg && P.hmc_L > 0 && P.hmc_k <= P.hmc_L) {
+        // leapfrog: kick with the force of this pass, drift unless last
+        const double c = (P.hmc_k == 0 || P.hmc_k == P.hmc_L) ? 0.5 * P.hmc_eps
+                                                              : P.hmc_eps;
+        const double p0 = P.pmom[i];
+        const double p1 = p0 - c * g / P.T;
+        P.pmom[i] = p1;
+        k0 = p0 * p0;
+        k1 = p1 * p1;
+        nf |= !isfinite(p1);
+        if (P.hmc_k < P.hmc_L) {
+          const double nphi = ph + P.hmc_eps * p1;
+          nf |= !isfinite(nphi);
+          P.phi_out[i] = nphi;
+        }
+      }
       if (adam && dg && P.steps_left > 0) {
         const int t = P.adam_t + 1;
         const double m = P.beta1 * P.m[i] + (1.0 - P.beta1) * g;
@@ -163,21 +180,26 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
     red_s[1][site_l] = stag;
     red_s[2][site_l] = ga;
     red_s[3][site_l] = hm;
+    red_s[4][site_l] = k0;
+    red_s[5][site_l] = k1;
     nf_s[site_l] = nf;
   }
   __syncthreads();
   if (tid == 0) {
-    double a = 0.0, b = 0.0, c = 0.0, h = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0, h = 0.0, k0 = 0.0, k1 = 0.0;
     int nf = 0;
     for (int q = 0; q < kSitesPerBlock; ++q) {
       a += red_s[0][q];
       b += red_s[1][q];
       c = fmax(c, red_s[2][q]);
       h = fmax(h, red_s[3][q]);
+      k0 += red_s[4][q];
+      k1 += red_s[5][q];
       nf |= nf_s[q];
     }
     ChunkPartial cp;
-    cp.phi2 = a; cp.stag = b; cp.gmax = c; cp.hmax = h; cp.nonfinite = nf; cp.pad_ = 0;
+    cp.phi2 = a; cp.stag = b; cp.gmax = c; cp.hmax = h; cp.kin0 = k0; cp.kin = k1;
+    cp.nonfinite = nf; cp.pad_ = 0;
     part[p * kMaxChunks + chunk] = cp;
   }
 }
@@ -189,7 +211,7 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
                       const ChunkPartial* __restrict__ part, int nchunks,
                       ProbStats* __restrict__ stats, int advance,
                       const double* __restrict__ mom,
-                      const double* __restrict__ tsum) {
+                      const double* __restrict__ tsum, int hmc) {
   const int p = blockIdx.x;
   const ProbDesc P = probs[p];
   const int tid = threadIdx.x;
@@ -231,12 +253,13 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
     __syncthreads();
   }
   if (tid == 0) {
-    double phi2 = 0.0, stag = 0.0, gmax = 0.0, hmax = 0.0;
+    double phi2 = 0.0, stag = 0.0, gmax = 0.0, hmax = 0.0, k0 = 0.0, k1 = 0.0;
     int nf = 0;
     for (int c = 0; c < nchunks; ++c) {
       const ChunkPartial cp = part[p * kMaxChunks + c];
       phi2 += cp.phi2; stag += cp.stag; gmax = fmax(gmax, cp.gmax);
       hmax = fmax(hmax, cp.hmax);
+      k0 += cp.kin0; k1 += cp.kin;
       nf |= cp.nonfinite;
     }
     ProbStats S;
@@ -248,12 +271,15 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
     nf |= !isfinite(S.omega) || !isfinite(S.omega_tilde);
     S.nonfinite = nf;
     S.tail_range = (P.Me < P.M && !(hmax + 4.0 * fabs(P.t) <= P.tail_guard)) ? 1 : 0;
+    S.kin0 = 0.5 * k0;
+    S.kin = 0.5 * k1;
     stats[p] = S;
     // the site kernel of this pass has read adam_t and steps_left already
     if (advance && P.steps_left > 0) {
       probs[p].adam_t = P.adam_t + 1;
       probs[p].steps_left = P.steps_left - 1;
     }
+    if (hmc && P.hmc_L > 0) probs[p].hmc_k = P.hmc_k + 1;
   }
 }
 
@@ -267,7 +293,7 @@ hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
                          const double* dg, const double* growth,
                          ProbStats* stats, bool adam, void* ws,
                          const double* mom, const double* tsum,
-                         hipStream_t st) {
+                         hipStream_t st, bool hmc) {
   if (nprob <= 0) return hipSuccess;
   const int nchunks = (N + kSitesPerBlock - 1) / kSitesPerBlock;
   if (nchunks > kMaxChunks) return hipErrorInvalidValue;
@@ -275,12 +301,13 @@ hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
   mark_begin(K_REDUCE, st);
   hipLaunchKernelGGL(site_reduce_kernel, dim3(nchunks, nprob),
                      dim3(kReduceThreads), 0, st, probs, N, dg, part,
-                     (int)adam, mom, tsum);
+                     (int)adam, mom, tsum, (int)(hmc && dg != nullptr));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(problem_reduce_kernel, dim3(nprob), dim3(256), 0, st,
                      probs, N, lad, growth, part, nchunks, stats,
-                     (int)(adam && dg != nullptr), mom, tsum);
+                     (int)(adam && dg != nullptr), mom, tsum,
+                     (int)(hmc && dg != nullptr));
   mark_end(K_REDUCE, st);
   return hipGetLastError();
 }

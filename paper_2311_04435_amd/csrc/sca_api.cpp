@@ -161,7 +161,7 @@ hipError_t enqueue_pass(const Carve& c, int nprob, int L, int B,
                      c.growth, c.fact, st);
   if (e == hipSuccess)
     e = launch_reduce(c.probs, nprob, N, c.lad, c.dg, c.growth, c.stats, adam,
-                      c.rws, c.mom, c.tsum, st);
+                      c.rws, c.mom, c.tsum, st, c.hmc_on);
   return e;
 }
 
@@ -287,6 +287,7 @@ Carve carve(char* base, int nprob, int N, int B, int precision,
   c.mom = (double*)take(tail_workspace_bytes(nprob, N));
   c.tsum = c.mom ? c.mom + (size_t)nprob * 2 * kTailP * N : nullptr;
   c.tail_on = false;
+  c.hmc_on = false;
   c.fact = fact_bytes ? (void*)take(fact_bytes) : nullptr;
   (void)precision;
   c.total = off;
@@ -571,6 +572,82 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
     res->flags |= SCA_FLAG_NONFINITE;
     return fail(SCA_ENUMERIC, "non-finite value in the solve");
   }
+  return SCA_OK;
+}
+
+sca_status sca_hmc(sca_ctx* ctx, const sca_params* p, const sca_hmc_opts* o,
+                   double* phi, const double* momenta, const double* uniforms,
+                   int32_t* accepted, double* h_old, double* h_new) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  if (!o) return fail(SCA_EINVAL, "opts is NULL");
+  if (!(o->eps > 0.0) || !std::isfinite(o->eps) || o->n_leap < 1 ||
+      o->n_traj < 0)
+    return fail(SCA_EINVAL, "eps > 0, n_leap >= 1 and n_traj >= 0 required");
+  if (o->n_traj > 0 && (!uniforms || !accepted || !h_old || !h_new))
+    return fail(SCA_EINVAL, "uniforms, accepted, h_old, h_new must be host "
+                "arrays of n_traj");
+  DeviceGuard g(ctx, ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if (o->n_traj > 0 && (s = check_dev_ptr(ctx, momenta, "momenta"))) return s;
+  const int N = p->L * p->L;
+  const int prec = route_of(p);
+  ProbDesc P = make_prob(p, phi, nullptr);
+  if ((s = plan_tail(ctx, p, phi, P))) return s;
+  const int B = 2 * P.Me;
+  const size_t fb = factor_workspace_bytes(N, B, prec);
+  Carve c0 = carve(nullptr, 1, N, B, prec, true, true, fb);
+  // momentum and the trajectory's starting phi after the carve
+  const size_t extra = 2 * ((sizeof(double) * N + 255) & ~size_t(255));
+  if ((s = ensure_ws(ctx, c0.total + extra))) return s;
+  Carve c = carve((char*)ctx->ws, 1, N, B, prec, true, true, fb);
+  c.tail_on = P.Me < P.M;
+  c.hmc_on = true;
+  double* pmom = (double*)((char*)ctx->ws + c0.total);
+  double* phi0 = (double*)((char*)pmom + extra / 2);
+  P.phi_out = phi;
+  P.pmom = pmom;
+  P.hmc_eps = o->eps;
+  P.hmc_L = o->n_leap;
+  hipStream_t st = ctx->stream;
+  if ((s = ensure_pinned(ctx, 2 * sizeof(ProbStats) + sizeof(ProbDesc))))
+    return s;
+  ProbStats* pin = (ProbStats*)ctx->pinned;
+  for (int t = 0; t < o->n_traj; ++t) {
+    HIP_TRY(hipMemcpyAsync(pmom, momenta + (size_t)t * N, sizeof(double) * N,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(phi0, phi, sizeof(double) * N,
+                           hipMemcpyDeviceToDevice, st));
+    // pass 0 (descriptors uploaded, hmc_k = 0), then passes 1 .. L
+    P.hmc_k = 0;
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(pin + 2, &P, sizeof P);
+    HIP_TRY(hipMemcpyAsync(c.probs, pin + 2, sizeof P, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_matsubara_descs(c.probs, 1, B, c.descs, st));
+    for (int k = 0; k <= o->n_leap; ++k) {
+      HIP_TRY(enqueue_pass(c, 1, p->L, B, prec, false, st));
+      if (k == 0)
+        HIP_TRY(hipMemcpyAsync(pin, c.stats, sizeof(ProbStats),
+                               hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipMemcpyAsync(pin + 1, c.stats, sizeof(ProbStats),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const ProbStats S0 = pin[0], S1 = pin[1];
+    if (S0.nonfinite || S1.nonfinite)
+      return fail(SCA_ENUMERIC, "non-finite value in trajectory %d", t);
+    if (S0.tail_range || S1.tail_range)
+      return fail(SCA_ENUMERIC, "trajectory %d left the Matsubara tail's "
+                  "range: sample with tail = SCA_TAIL_NONE", t);
+    h_old[t] = S0.omega_tilde / p->T + S0.kin0;
+    h_new[t] = S1.omega_tilde / p->T + S1.kin;
+    const double dh = h_new[t] - h_old[t];
+    accepted[t] = (dh <= 0.0 || uniforms[t] < std::exp(-dh)) ? 1 : 0;
+    if (!accepted[t])
+      HIP_TRY(hipMemcpyAsync(phi, phi0, sizeof(double) * N,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
   return SCA_OK;
 }
 

@@ -38,6 +38,13 @@ struct ProbDesc {
                          // the moment expansion of the tail (Me == M: none)
   double tail_guard;     // tail only: flag a pass whose Gershgorin bound on
                          // the spectral radius of H exceeds this
+  // Hybrid Monte Carlo (hmc_L > 0): pass k of a trajectory evaluates the
+  // force at phi_k, then p -= c_k grad/T (c_0 = c_L = eps/2, else eps) and,
+  // for k < L, phi += eps p
+  double* pmom;          // [N] momentum
+  double hmc_eps;        // leapfrog step
+  int32_t hmc_L;         // leapfrog steps per trajectory (0: no HMC)
+  int32_t hmc_k;         // passes done in the current trajectory
 };
 
 // Matsubara tail by moments.  For w > rho(H),
@@ -53,6 +60,7 @@ struct ProbStats {
   double omega, omega_tilde, max_abs_grad, af_order, pivot_growth;
   int32_t nonfinite;
   int32_t tail_range;   // the tail's spectral bound exceeded its guard
+  double kin0, kin;     // HMC: 1/2 sum p^2 before and after this pass's kick
 };
 
 // Number of lattice directions d in {+x,-x,+y,-y} with j = i + d (mod L).

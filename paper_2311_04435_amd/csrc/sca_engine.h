@@ -46,6 +46,7 @@ struct Carve {
   double* dg; void* rws; ProbStats* stats; void* fact;
   double* mom; double* tsum;   // Matsubara tail (moments, frequency sums)
   bool tail_on;                // some problem of the batch has Me < M
+  bool hmc_on;                 // leapfrog updates in the reduction
   size_t total;
 };
 Carve carve(char* base, int nprob, int N, int B, int precision, bool own_dg,

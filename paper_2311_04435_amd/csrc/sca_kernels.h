@@ -30,11 +30,13 @@ hipError_t launch_small_factor(const MatDesc* descs, const double* hbuf, int B,
 // the phi the terms were evaluated at) and the largest pivot growth of the
 // problem's matrices.
 // Problems with Me < M add their tail from mom / tsum (launch_tail).
+// With `hmc`, problems with hmc_L > 0 take the leapfrog kick/drift of their
+// pass hmc_k instead (and advance hmc_k).
 hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
                          const double* dg, const double* growth,
                          ProbStats* stats, bool adam, void* ws,
                          const double* mom, const double* tsum,
-                         hipStream_t st);
+                         hipStream_t st, bool hmc = false);
 size_t reduce_workspace_bytes(int nprob);
 int reduce_max_sites();
 

@@ -41,6 +41,19 @@ def uniform(seed: int, count: int, lo: float, hi: float) -> np.ndarray:
     return lo + (hi - lo) * u
 
 
+def normal(seed: int, count: int) -> np.ndarray:
+    """`count` standard normal doubles (Box-Muller on pairs of uniforms from
+    `uniform`; the first uniform of each pair is moved into (0, 1])."""
+    m = (count + 1) // 2
+    u = uniform(seed, 2 * m, 0.0, 1.0)
+    u1, u2 = 1.0 - u[0::2], u[1::2]
+    r = np.sqrt(-2.0 * np.log(u1))
+    z = np.empty(2 * m)
+    z[0::2] = r * np.cos(2.0 * np.pi * u2)
+    z[1::2] = r * np.sin(2.0 * np.pi * u2)
+    return z[:count]
+
+
 def rademacher(seed: int, count: int) -> np.ndarray:
     """`count` independent +-1.0 values (bit 63 of each SplitMix64 output)."""
     return np.where(splitmix64(seed, count) >> np.uint64(63), -1.0, 1.0)

@@ -389,3 +389,48 @@ def test_oracle_disordered_routes_agree():
     g_d = oracle.grad_d(p, phi, onsite=eps)
     assert abs(om_s - om_d) <= 1e-13 * abs(om_s)
     assert np.max(np.abs(g_s - g_d)) <= 1e-13 * np.max(np.abs(g_s))
+
+
+# ---- Hybrid Monte Carlo of exp(-Omega/T) (oracle.hmc) ------------------------
+
+def _hmc_case():
+    p = dict(L=4, t=1.0, U=3.0, delta=0.4, T=0.3, n_max=64)
+    phi = synth.uniform(31, 16, -0.6, 0.6)
+    mom = synth.normal(32, 16)
+    return p, phi, mom
+
+
+def test_hmc_leapfrog_reversible():
+    """Integrating forward, negating the momentum and integrating again
+    returns to the start (a sign or half-step slip breaks this)."""
+    p, phi, mom = _hmc_case()
+    phi1, mom1 = oracle.leapfrog(p, phi, mom, 0.02, 12)
+    phi2, mom2 = oracle.leapfrog(p, phi1, -mom1, 0.02, 12)
+    assert np.max(np.abs(phi2 - phi)) < 1e-12
+    assert np.max(np.abs(-mom2 - mom)) < 1e-11
+
+
+def test_hmc_energy_error_second_order():
+    """|H_end - H_start| falls as eps^2 at fixed trajectory length."""
+    p, phi, mom = _hmc_case()
+    h0 = oracle.hmc_hamiltonian(p, phi, mom)
+    dh = []
+    for eps, n in ((0.02, 10), (0.01, 20), (0.005, 40)):
+        phi1, mom1 = oracle.leapfrog(p, phi, mom, eps, n)
+        dh.append(abs(oracle.hmc_hamiltonian(p, phi1, mom1) - h0))
+    r1, r2 = dh[0] / dh[1], dh[1] / dh[2]
+    print("dH:", dh, "ratios", r1, r2)
+    assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0
+    # the trajectory moves phi by much more than its energy error
+    phi1, _ = oracle.leapfrog(p, phi, mom, 0.02, 10)
+    assert np.max(np.abs(phi1 - phi)) > 1e-2
+
+
+def test_hmc_acceptance_rule():
+    p, phi, mom = _hmc_case()
+    moms = np.stack([mom, synth.normal(33, 16)])
+    # u = 1 - tiny accepts only downhill moves; u = 0 accepts everything
+    _, acc0, h0, h1 = oracle.hmc_chain(p, phi, moms, [0.0, 0.0], 0.05, 6)
+    assert list(acc0) == [1, 1]
+    _, acc1, h0, h1 = oracle.hmc_chain(p, phi, moms, [1.0 - 1e-15] * 2, 0.05, 6)
+    assert list(acc1) == [int(h1[0] <= h0[0]), int(h1[1] <= h0[1])]
