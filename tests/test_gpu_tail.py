@@ -63,6 +63,23 @@ def test_tail_grad(sca, name, factor):
     assert e_om < 1e-10 and e_g < 1e-10 and e_f < 1e-10
 
 
+@pytest.mark.parametrize("L,precision,tol", [(6, "fp64", 1e-10),
+                                             (16, "fp32r", 1e-10)])
+def test_tail_other_paths(sca, L, precision, tol):
+    """The fused small path (N <= 64) and the FP32-refined route with the
+    tail."""
+    p = sca.Params(L=L, U=4.0, T=0.1, n_max=256, delta=0.6,
+                   precision=precision, tail=True)
+    phi = synth.uniform(1600 + L, L * L, -0.5, 0.5)
+    g, o2 = sca.grad(p, cuda(phi))
+    om = oracle.omega_tilde(pd(p), phi)
+    gr = oracle.grad(pd(p), phi)
+    e_om = abs(o2[1].item() - om) / abs(om)
+    e_g = grad_err(g.cpu().numpy(), gr, phi, p.U)
+    print(f"L={L} {precision} tail: Omega~ {e_om:.1e} grad {e_g:.1e}")
+    assert e_om < tol and e_g < tol
+
+
 def test_tail_matches_full_gpu(sca):
     """Tail and all-frequency evaluations on the GPU agree to rounding."""
     wl = synth.WORKLOADS["hubbard_20x20_T0.6"]
