@@ -27,7 +27,8 @@ Prints one JSON line.  Besides the contract fields it carries
                 then symmetric), with n_factorised and their rooflines;
   serving       served solves/s and p50/p99 latency of a Poisson stream of
                 mixed requests through the request server, next to the
-                one-at-a-time FIFO baseline on the same GPU.
+                one-at-a-time FIFO baseline on the same GPU;
+  serving_tail  the same stream with the Matsubara tail by moments.
 """
 from __future__ import annotations
 
@@ -250,7 +251,7 @@ def route_line(sca, name, prec, factor, steps, warmup, tail=False):
 
 
 def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0,
-            factor="lu"):
+            factor="lu", tail=False):
     """Poisson stream of mixed requests: one at a time (FIFO, measured
     service times) vs the request server (real time)."""
     import numpy as np
@@ -260,7 +261,7 @@ def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0,
                                             latency_summary)
     reqs = []
     for r in synth.serving_stream(n_req, seed, n_max, Ls=Ls):
-        p = sca.Params.from_dict(r["params"], factor=factor)
+        p = sca.Params.from_dict(r["params"], factor=factor, tail=tail)
         phi0 = torch.as_tensor(synth.make_phi0(p.L, r["phi0"]),
                                dtype=torch.float64).cuda()
         reqs.append(dict(params=p, phi0=phi0, n_steps=steps))
@@ -295,7 +296,8 @@ def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0,
     del ctx
     return {"workload": (f"{n_req} requests, L in {sorted(set(Ls))}, "
                          f"n_max={n_max}, {steps} ADAM steps each, FP64 "
-                         f"({'pivoted LU' if factor == 'lu' else 'L D L^T'}), "
+                         f"({'pivoted LU' if factor == 'lu' else 'L D L^T'}"
+                         f"{', Matsubara tail by moments' if tail else ''}), "
                          f"U~U[2,8], Delta~U[0,2], T~U[0.05,0.6]"),
             "arrivals": f"Poisson, {rate:.3f}/s = {load} x FIFO capacity",
             "max_batch": max_batch,
@@ -456,6 +458,14 @@ def main():
         out["serving"] = serving(sca, args.serving_requests, args.serving_steps,
                                  args.serving_nmax, Ls, args.serving_batch,
                                  factor=args.serving_factor)
+        if not args.no_tail:
+            # the same stream with the high frequencies from the moments
+            out["serving_tail"] = serving(sca, args.serving_requests,
+                                          args.serving_steps,
+                                          args.serving_nmax, Ls,
+                                          args.serving_batch,
+                                          factor=args.serving_factor,
+                                          tail=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
