@@ -67,7 +67,7 @@ typedef enum {
 typedef enum { SCA_FP64 = 0, SCA_FP32_REFINED = 1 } sca_precision;
 
 /* Factorisation of each A = z I - H (lattices with L*L > 64; smaller ones
- * always use the fused pivoted LU).
+ * always use the fused pivoted LU, except under SCA_FACTOR_EIGH).
  *   SCA_FACTOR_LU    complex LU with partial pivoting (the default).
  *   SCA_FACTOR_LDLT  A is complex symmetric: A = L D L^T without pivoting,
  *                    half the flops and one triangular inverse instead of
@@ -76,7 +76,22 @@ typedef enum { SCA_FP64 = 0, SCA_FP32_REFINED = 1 } sca_precision;
  *                    max|A|, max|L|) exceeds 64 or whose pivots are not
  *                    finite is redone by the pivoted LU on the device.
  *                    FP64 only (SCA_EUNSUPPORTED with SCA_FP32_REFINED). */
-typedef enum { SCA_FACTOR_LU = 0, SCA_FACTOR_LDLT = 1 } sca_factor;
+/*   SCA_FACTOR_EIGH  spectral route, any L: no matrix is factorised.  Each
+ *                    H_s is real symmetric; H_s = sum_k e_k psi_k psi_k^T
+ *                    is computed once per spin and evaluation (Householder
+ *                    tridiagonalisation, bisection, inverse iteration), and
+ *                    every shift then follows from the spectrum:
+ *                    ln|det(z - H_s)| = sum_k ln|z - e_k|,
+ *                    (z - H_s)^-1_ii = sum_k psi_k(i)^2 / (z - e_k).
+ *                    O(N^3 + n_max N^2) per spin instead of O(n_max N^3).
+ *                    FP64 only (SCA_EUNSUPPORTED with SCA_FP32_REFINED and
+ *                    in sca_factorize / sca_grad_from_factors, whose buffer
+ *                    holds factors).  max_pivot_growth reads 1.  An
+ *                    eigenvector cluster that loses rank in its
+ *                    orthogonalisation is reported as non-finite
+ *                    (SCA_ENUMERIC / SCA_FLAG_NONFINITE). */
+typedef enum { SCA_FACTOR_LU = 0, SCA_FACTOR_LDLT = 1,
+               SCA_FACTOR_EIGH = 2 } sca_factor;
 
 /* Matsubara frequencies that are factorised.
  *   SCA_TAIL_NONE     all n < n_max (the default).
@@ -249,6 +264,10 @@ SCA_API sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
 #define SCA_K_TRTRI_SYM 9  /* symmetric route: L^-T */
 #define SCA_K_SYMDIAG 10   /* symmetric route: diagonal of A^-1 */
 #define SCA_K_FALLBACK 11  /* symmetric route: pivoted LU of flagged matrices */
+#define SCA_K_TAIL 12      /* Matsubara tail: moments of H, frequency sums */
+#define SCA_K_TRIDIAG 13   /* spectral route: Householder tridiagonalisation */
+#define SCA_K_SPECTRUM 14  /* spectral route: eigenpairs and psi^2 */
+#define SCA_K_EXPAND 15    /* spectral route: per-shift terms from the spectrum */
 SCA_API sca_status sca_profile(sca_ctx* ctx, int enable);
 SCA_API sca_status sca_profile_read(sca_ctx* ctx, double* total_ms,
                                     int64_t* launches);

@@ -24,7 +24,8 @@ from ._lib import (SCAError, SCA_FP64, SCA_FP32_REFINED,  # noqa: F401
                    SCA_FLAG_CONVERGED, SCA_FLAG_TAIL_RANGE)
 
 PRECISIONS = {"fp64": SCA_FP64, "fp32r": SCA_FP32_REFINED}
-FACTORS = {"lu": _lib.SCA_FACTOR_LU, "ldlt": _lib.SCA_FACTOR_LDLT}
+FACTORS = {"lu": _lib.SCA_FACTOR_LU, "ldlt": _lib.SCA_FACTOR_LDLT,
+           "eigh": _lib.SCA_FACTOR_EIGH}
 
 
 @dataclasses.dataclass(frozen=True)
@@ -33,7 +34,8 @@ class Params:
     ionic amplitude delta (site potential +-delta/2), temperature T > 0,
     n_max Matsubara frequencies per sign, precision 'fp64' | 'fp32r',
     factorisation 'lu' (pivoted, default) | 'ldlt' (symmetric, unpivoted,
-    FP64), an optional extra site potential `onsite` (float64 CUDA tensor
+    FP64) | 'eigh' (spectral route, FP64: one eigendecomposition of H per
+    spin, every frequency from the spectrum), an optional extra site potential `onsite` (float64 CUDA tensor
     of N) and `tail`: factorise only the Matsubara frequencies below about
     4x a bound on the spectral radius of H and take the rest from the
     moments of H (the same sums, evaluated by a series whose truncation

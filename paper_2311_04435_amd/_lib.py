@@ -16,7 +16,7 @@ SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EDEVICE, SCA_ENUMERIC, SCA_EUNSUPPORTED = \
 STATUS_NAMES = {0: "SCA_OK", -1: "SCA_EINVAL", -2: "SCA_ENOMEM",
                 -3: "SCA_EDEVICE", -4: "SCA_ENUMERIC", -5: "SCA_EUNSUPPORTED"}
 SCA_FP64, SCA_FP32_REFINED = 0, 1
-SCA_FACTOR_LU, SCA_FACTOR_LDLT = 0, 1
+SCA_FACTOR_LU, SCA_FACTOR_LDLT, SCA_FACTOR_EIGH = 0, 1, 2
 SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH, SCA_FLAG_CONVERGED = 1, 2, 4
 SCA_FLAG_TAIL_RANGE = 8
 SCA_TAIL_NONE, SCA_TAIL_MOMENTS = 0, 1
@@ -24,7 +24,7 @@ SCA_ADAM_NO_FINAL_EVAL = 1
 PROFILE_SLOTS = 16
 KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
                   "refine", "wvgemm", "ldlt", "trtri_sym", "symdiag",
-                  "fallback", "tail", "spare13", "spare14", "spare15")
+                  "fallback", "tail", "tridiag", "spectrum", "expand")
 
 # Every symbol include/sca.h declares.
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",

@@ -32,6 +32,14 @@ class SCAPotential(torch.autograd.Function):
         c = default_context()
         contiguous = phi.is_contiguous()
         x = phi.detach() if contiguous else phi.detach().contiguous()
+        if p.factor == "eigh":
+            # the spectral route keeps no factors: its gradient costs the
+            # same pass as the potential, so the forward keeps it
+            g, o2 = c.grad(p, x)
+            ctx.save_for_backward(phi if contiguous else x)
+            ctx.sca = (c, p, g)
+            ctx.used = False
+            return o2
         factors = torch.empty(c.factor_bytes(p), dtype=torch.uint8,
                               device=x.device)
         o2 = c.factorize(p, x, factors)
@@ -47,6 +55,8 @@ class SCAPotential(torch.autograd.Function):
     def backward(ctx, gout: torch.Tensor):
         (phi,) = ctx.saved_tensors
         c, p, factors = ctx.sca
+        if p.factor == "eigh":
+            return factors * (gout[0] + gout[1]), None
         x = phi.detach().contiguous()
         if ctx.used:
             # a repeated backward (retain_graph): the FP64 blocked path has

@@ -1,0 +1,657 @@
+// Spectral route: one eigendecomposition of each real symmetric
+// H = -t K + diag(h) of the batch, then every matrix A_b = z_b I - H from the
+// spectrum,
+//   ln|det A_b|      = sum_k ln|z_b - lambda_k|
+//   (A_b^-1)_ii      = sum_k psi_k(i)^2 / (z_b - lambda_k)
+// (H = sum_k lambda_k psi_k psi_k^T; the determinant is the product of the
+// eigenvalues of A_b and the resolvent is diagonal in the eigenbasis).  The
+// per-matrix outputs are the ones the factorisation routes write, so the
+// Matsubara/spin reduction downstream is shared.
+//
+// The eigendecomposition follows the Householder / bisection / inverse
+// iteration scheme (Golub & Van Loan, Sec. 8.3-8.4; LAPACK's dsytrd, dstebz,
+// dstein describe the same steps):
+//   eig_init_kernel    dense H and Q = I per h vector
+//   hh_step_kernel     one launch per column j: the pending reflector of
+//                      column j-1 is applied to the trailing block of the
+//                      workgroup's rows (and to Q); column j is formed from
+//                      the previous launch's copy, its reflector built
+//                      (redundantly in every workgroup) and p = tau A v of
+//                      the workgroup's rows written for the next launch.
+//                      Q H Q^T-form: H = Q T Q^T, T tridiagonal (d, e).
+//   bisect_kernel      T splits where |e_i| <= 2 eps |T|; one wave per
+//                      eigenvalue: 64 Sturm counts per round (65-section),
+//                      ten rounds.
+//   invit_kernel       one lane per eigenvalue: pivoted LU of T_blk - lambda,
+//                      three solves from a counter-hashed start vector.
+//   mgs_kernel         eigenvalues of one block closer than 1e-3 |T_blk| form
+//                      a cluster; its vectors are orthonormalised (modified
+//                      Gram-Schmidt, two passes) in index order.
+//   psi_sq_kernel      P = (Q Z) o (Q Z) (tiled GEMM, squared in the epilogue)
+//   expand_kernel      dg[b][i] = sum_k P_ik / (z_b - lambda_k)
+//   lad_kernel         lad[b] = sum_k ln|z_b - lambda_k|, growth[b] = 1
+#include <float.h>
+#include <math.h>
+#include "sca_common.h"
+#include "sca_kernels.h"
+#include "sca_profile.h"
+#include "sca_runtime.h"
+
+namespace sca {
+
+namespace {
+
+constexpr int kRowsPerWg = 4;     // hh_step: one wave per row
+constexpr int kBisRounds = 10;    // 65^-10 of the Gershgorin width
+constexpr int kInvIters = 3;
+constexpr double kEps = DBL_EPSILON;
+constexpr double kClusterTol = 1e-3;
+constexpr double kSplitTol = 2.0;   // split where |e_i| <= kSplitTol eps |T|
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ inline double wave_maxd(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline double wave_mind(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline int wave_maxi(int v) {
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline int wave_mini(int v) {
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+  return v;
+}
+
+// sum over the 256 threads of a workgroup (every thread gets the result)
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// uniform in (-1, 1) from a 64-bit counter (SplitMix64 finaliser)
+__device__ inline double hash_uniform(unsigned long long x) {
+  x += 0x9E3779B97F4A7C15ULL;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+  x ^= x >> 31;
+  return (double)(x >> 11) * 0x1.0p-52 - 1.0;
+}
+
+}  // namespace
+
+struct EigBufs {
+  double* A;      // [nH][N][N] working matrix; later Z (eigenvectors of T)
+  double* Q;      // [nH][N][N] accumulated reflectors
+  double* P;      // [nH][N][N] psi^2
+  double* lu;     // [nH][4][N][N] u0^-1, u1, u2, m of T_blk - lambda_t,
+                  //  element (local row j, eigenvalue t) at j * N + t
+  unsigned char* piv;   // [nH][N][N] row swap of elimination step j
+  double* vec;    // [nH][6][N] v[2], p[2], col[2] (parity of the column)
+  double* tau;    // [nH][2]
+  double* d;      // [nH][N] diagonal of T
+  double* e;      // [nH][N] off-diagonal of T (e[i] couples i, i+1)
+  double* lam;    // [nH][N] eigenvalues (ascending inside each block)
+  double* bnorm;  // [nH][N] |T_blk| of the block of eigenvalue t
+  int* bnd;       // [nH][2][N] block [b0, b1) of eigenvalue t
+};
+
+size_t eig_workspace_bytes(int N, int nH) {
+  const size_t n2 = (size_t)nH * N * N, n1 = (size_t)nH * N;
+  return 3 * al256(sizeof(double) * n2) + al256(sizeof(double) * 4 * n2) +
+         al256(n2) + al256(sizeof(double) * 6 * n1) +
+         al256(sizeof(double) * 2 * nH) + 4 * al256(sizeof(double) * n1) +
+         al256(sizeof(int) * 2 * n1);
+}
+
+static EigBufs carve_eig(void* ws, int N, int nH) {
+  const size_t n2 = (size_t)nH * N * N, n1 = (size_t)nH * N;
+  char* c = static_cast<char*>(ws);
+  EigBufs E;
+  auto take = [&](size_t bytes) { char* r = c; c += al256(bytes); return r; };
+  E.A = (double*)take(sizeof(double) * n2);
+  E.Q = (double*)take(sizeof(double) * n2);
+  E.P = (double*)take(sizeof(double) * n2);
+  E.lu = (double*)take(sizeof(double) * 4 * n2);
+  E.piv = (unsigned char*)take(n2);
+  E.vec = (double*)take(sizeof(double) * 6 * n1);
+  E.tau = (double*)take(sizeof(double) * 2 * nH);
+  E.d = (double*)take(sizeof(double) * n1);
+  E.e = (double*)take(sizeof(double) * n1);
+  E.lam = (double*)take(sizeof(double) * n1);
+  E.bnorm = (double*)take(sizeof(double) * n1);
+  E.bnd = (int*)take(sizeof(int) * 2 * n1);
+  return E;
+}
+
+// grid (N, nH): row i of H_hv (hopping of problem hv / 2) and of Q = I
+__global__ void __launch_bounds__(256)
+eig_init_kernel(const ProbDesc* __restrict__ probs, const double* __restrict__ hbuf,
+                int N, int L, EigBufs E) {
+  const int i = blockIdx.x, hv = blockIdx.y;
+  const double t = probs[hv >> 1].t;
+  const double hi = hbuf[(size_t)hv * N + i];
+  double* A = E.A + ((size_t)hv * N + i) * N;
+  double* Q = E.Q + ((size_t)hv * N + i) * N;
+  for (int j = threadIdx.x; j < N; j += 256) {
+    A[j] = -t * (double)kmult(i, j, L) + (i == j ? hi : 0.0);
+    Q[j] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+// Householder step j (0 <= j < N), grid (ceil(N / 4), nH), 256 threads.
+// The reflector of column j-1 (v, tau, p = tau A_{j-1} v: support [j, N))
+// is pending from the previous launch; w = p - (tau/2)(p.v) v and
+// A_j = A_{j-1} - v w^T - w v^T on [j, N)^2, Q <- Q (I - tau v v^T).
+// Column j of A_j is formed from the previous launch's copy of column j of
+// A_{j-1}; its entries below the diagonal give the reflector of column j
+// (v_{j+1} = 1, tau = (beta - alpha)/beta, beta = -sign(alpha) |x|).
+__global__ void __launch_bounds__(256)
+hh_step_kernel(int N, int j, EigBufs E) {
+  const int hv = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r = blockIdx.x * kRowsPerWg + w;   // this wave's row
+  double* A = E.A + (size_t)hv * N * N;
+  double* Q = E.Q + (size_t)hv * N * N;
+  double* vb = E.vec + (size_t)hv * 6 * N;
+  double* taub = E.tau + 2 * hv;
+  extern __shared__ double sm[];
+  double* sv = sm;            // pending v
+  double* sw = sm + N;        // pending w
+  double* sx = sm + 2 * N;    // column j of A_j, then the new v
+  __shared__ double red[4];
+  const int cur = j & 1, prv = cur ^ 1;
+  const bool pend = j > 0;
+  double tp = 0.0;
+  if (pend) {
+    tp = taub[prv];
+    const double* vp = vb + prv * N;
+    const double* pp = vb + (2 + prv) * N;
+    double s = 0.0;
+    for (int c = j + tid; c < N; c += 256) {
+      const double a = vp[c], b = pp[c];
+      sv[c] = a; sw[c] = b; s += a * b;
+    }
+    s = block_sum(s, red);
+    const double K = 0.5 * tp * s;
+    for (int c = j + tid; c < N; c += 256) sw[c] -= K * sv[c];
+  }
+  __syncthreads();
+  // column j of A_j, rows [j, N)
+  if (!pend) {
+    for (int q = tid; q < N; q += 256) sx[q] = A[(size_t)q * N];
+  } else {
+    const double* cp = vb + (4 + prv) * N;
+    const double wj = sw[j], vj = sv[j];
+    for (int q = j + tid; q < N; q += 256) sx[q] = cp[q] - sv[q] * wj - sw[q] * vj;
+  }
+  // pending update of this wave's row
+  if (pend && r < N) {
+    if (r >= j) {
+      double* Ar = A + (size_t)r * N;
+      const double vr = sv[r], wr = sw[r];
+      for (int c = j + lane; c < N; c += 64) Ar[c] -= vr * sw[c] + wr * sv[c];
+    }
+    double* Qr = Q + (size_t)r * N;
+    double qv = 0.0;
+    for (int c = j + lane; c < N; c += 64) qv += Qr[c] * sv[c];
+    qv = wave_sum(qv) * tp;
+    for (int c = j + lane; c < N; c += 64) Qr[c] -= qv * sv[c];
+  }
+  __syncthreads();
+  if (j == N - 1) {   // last diagonal entry; no reflector
+    if (blockIdx.x == 0 && tid == 0) E.d[(size_t)hv * N + j] = sx[j];
+    return;
+  }
+  // reflector of column j from x = sx[j+1 .. N)
+  const double alpha = sx[j + 1];
+  double s = 0.0;
+  for (int q = j + 2 + tid; q < N; q += 256) s += sx[q] * sx[q];
+  s = block_sum(s, red);
+  double tau, beta, scale;
+  if (s == 0.0) {
+    tau = 0.0; beta = alpha; scale = 0.0;
+  } else {
+    const double nrm = sqrt(alpha * alpha + s);
+    beta = alpha >= 0.0 ? -nrm : nrm;
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  const double dj = sx[j];
+  __syncthreads();   // every thread has read alpha and dj
+  for (int q = j + 1 + tid; q < N; q += 256) sx[q] = (q == j + 1) ? 1.0 : sx[q] * scale;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid == 0) {
+      E.d[(size_t)hv * N + j] = dj;
+      E.e[(size_t)hv * N + j] = beta;
+      taub[cur] = tau;
+    }
+    double* vn = vb + cur * N;
+    for (int q = j + 1 + tid; q < N; q += 256) vn[q] = sx[q];
+  }
+  // p = tau A_j v and the copy of column j+1 of A_j, rows of this wave
+  if (r < N && r >= j + 1) {
+    const double* Ar = A + (size_t)r * N;
+    double pr = 0.0;
+    for (int c = j + 1 + lane; c < N; c += 64) pr += Ar[c] * sx[c];
+    pr = wave_sum(pr) * tau;
+    if (lane == 0) {
+      vb[(2 + cur) * N + r] = pr;
+      vb[(4 + cur) * N + r] = Ar[j + 1];
+    }
+  }
+}
+
+// Sturm count of T_blk - x (rows [b0, b1)): eigenvalues below x.
+__device__ inline int sturm_count(const double* __restrict__ d,
+                                  const double* __restrict__ e2, int b0, int b1,
+                                  double x, double pivmin) {
+  int c = 0;
+  double q = d[b0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  c += q < 0.0;
+  for (int i = b0 + 1; i < b1; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+// grid (ceil(N / 4), nH), 256 threads: one wave per eigenvalue t.  The
+// split points, the block of t and its Gershgorin interval come from
+// wave reductions; the interval then shrinks 65-fold per round.
+__global__ void __launch_bounds__(256)
+bisect_kernel(int N, EigBufs E) {
+  const int hv = blockIdx.y, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const double* d = E.d + (size_t)hv * N;
+  double* e = E.e + (size_t)hv * N;
+  extern __shared__ double sm[];
+  double* sd = sm;        // d
+  double* se2 = sm + N;   // e^2 with the splits set to zero
+  __shared__ double red[4];
+  // |T| (Gershgorin) over the whole matrix
+  double tn = 0.0;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    const double el = i > 0 ? fabs(e[i - 1]) : 0.0;
+    const double er = i < N - 1 ? fabs(e[i]) : 0.0;
+    tn = fmax(tn, fabs(d[i]) + el + er);
+  }
+  tn = wave_maxd(tn);
+  if (lane == 0) red[threadIdx.x >> 6] = tn;
+  __syncthreads();
+  tn = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const double split = kSplitTol * kEps * tn;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    sd[i] = d[i];
+    const double ei = i < N - 1 ? e[i] : 0.0;
+    se2[i] = fabs(ei) <= split ? 0.0 : ei * ei;
+  }
+  __syncthreads();
+  if (t >= N) return;
+  // block [b0, b1) of t: b0 - 1 = last split below t, b1 - 1 = first at/after t
+  int lo_s = -1, hi_s = N - 1;
+  for (int i = lane; i < N - 1; i += 64) {
+    if (se2[i] == 0.0) {
+      if (i < t) lo_s = max(lo_s, i);
+      else hi_s = min(hi_s, i);
+    }
+  }
+  const int b0 = wave_maxi(lo_s) + 1, b1 = wave_mini(hi_s) + 1;
+  double gl = DBL_MAX, gu = -DBL_MAX, bn = 0.0, emax = 0.0;
+  for (int i = b0 + lane; i < b1; i += 64) {
+    const double el = i > b0 ? sqrt(se2[i - 1]) : 0.0;
+    const double er = i < b1 - 1 ? sqrt(se2[i]) : 0.0;
+    gl = fmin(gl, sd[i] - el - er);
+    gu = fmax(gu, sd[i] + el + er);
+    bn = fmax(bn, fabs(sd[i]) + el + er);
+    emax = fmax(emax, i < b1 - 1 ? se2[i] : 0.0);
+  }
+  gl = wave_mind(gl); gu = wave_maxd(gu); bn = wave_maxd(bn); emax = wave_maxd(emax);
+  const int n = b1 - b0, k = t - b0;
+  const double pivmin = DBL_MIN * fmax(1.0, emax);
+  const double pad = 4.0 * kEps * bn * n + 2.0 * pivmin;
+  double lo = gl - pad, hi = gu + pad;
+  if (n > 1) {
+    for (int it = 0; it < kBisRounds; ++it) {
+      const double h = (hi - lo) / 65.0;
+      const double x = lo + (lane + 1) * h;
+      const int c = sturm_count(sd, se2, b0, b1, x, pivmin);
+      const int m = __popcll(__ballot(c <= k));
+      const double nlo = m > 0 ? lo + m * h : lo;
+      const double nhi = m < 64 ? lo + (m + 1) * h : hi;
+      lo = nlo; hi = nhi;
+    }
+  }
+  if (lane == 0) {
+    const size_t o = (size_t)hv * N + t;
+    E.lam[o] = n > 1 ? 0.5 * (lo + hi) : sd[t];
+    E.bnorm[o] = bn;
+    E.bnd[(size_t)hv * 2 * N + t] = b0;
+    E.bnd[(size_t)hv * 2 * N + N + t] = b1;
+  }
+}
+
+// grid (ceil(N / 64), nH), 64 threads: lane = eigenvalue t.  Column t of Z
+// (stored over A) is zero outside the block of t; inside it the inverse
+// iteration with T_blk - lambda_t = P L U (partial pivoting; pivots below
+// eps |T_blk| raised to it).
+__global__ void __launch_bounds__(64)
+invit_kernel(int N, EigBufs E) {
+  const int hv = blockIdx.y;
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= N) return;
+  const size_t o = (size_t)hv * N;
+  const double* d = E.d + o;
+  const double* e = E.e + o;
+  double* Z = E.A + (size_t)hv * N * N;
+  const size_t n2 = (size_t)N * N;
+  double* U0 = E.lu + (size_t)hv * 4 * n2;
+  double* U1 = U0 + n2;
+  double* U2 = U1 + n2;
+  double* Mm = U2 + n2;
+  unsigned char* Pv = E.piv + (size_t)hv * n2;
+  const int b0 = E.bnd[o * 2 + t], b1 = E.bnd[o * 2 + N + t];
+  const int n = b1 - b0;
+  const double lam = E.lam[o + t], bn = E.bnorm[o + t];
+  for (int q = 0; q < N; ++q)
+    if (q < b0 || q >= b1) Z[(size_t)q * N + t] = 0.0;
+  if (n == 1) { Z[(size_t)b0 * N + t] = 1.0; return; }
+  // the splits of the bisection (the block's own couplings are nonzero)
+  const double tol = kEps * bn;
+  // elimination; the current row holds (cd, cs) at columns (i, i+1)
+  double cd = d[b0] - lam, cs = e[b0];
+  for (int i = 0; i < n - 1; ++i) {
+    const double ci = e[b0 + i];
+    const double an = d[b0 + i + 1] - lam;
+    const double bnx = i + 1 < n - 1 ? e[b0 + i + 1] : 0.0;
+    const bool pv = fabs(ci) > fabs(cd);
+    double u0, u1, u2, m;
+    if (pv) {
+      u0 = ci; u1 = an; u2 = bnx;
+      m = cd / ci;
+      const double ncd = cs - m * an;
+      cs = -m * bnx;
+      cd = ncd;
+    } else {
+      if (cd == 0.0) cd = tol;
+      u0 = cd; u1 = cs; u2 = 0.0;
+      m = ci / cd;
+      cd = an - m * cs;
+      cs = bnx;
+    }
+    if (fabs(u0) < tol) u0 = u0 >= 0.0 ? tol : -tol;
+    const size_t ix = (size_t)i * N + t;
+    U0[ix] = 1.0 / u0; U1[ix] = u1; U2[ix] = u2; Mm[ix] = m; Pv[ix] = pv;
+  }
+  if (fabs(cd) < tol) cd = cd >= 0.0 ? tol : -tol;
+  U0[(size_t)(n - 1) * N + t] = 1.0 / cd;
+  double* x = Z + (size_t)b0 * N + t;   // x[i] at x[i * N]
+  double sc = 1.0;
+  for (int it = 0; it < kInvIters; ++it) {
+    // forward: L^-1 P (sc * y), y = start vector on the first pass
+    double carry = it == 0 ? hash_uniform(((unsigned long long)t << 32) | 0u)
+                           : sc * x[0];
+    for (int i = 0; i < n - 1; ++i) {
+      const size_t ix = (size_t)i * N + t;
+      const double y = it == 0 ? hash_uniform(((unsigned long long)t << 32) |
+                                              (unsigned)(i + 1))
+                               : sc * x[(size_t)(i + 1) * N];
+      const double m = Mm[ix];
+      if (Pv[ix]) { x[(size_t)i * N] = y; carry = carry - m * y; }
+      else { x[(size_t)i * N] = carry; carry = y - m * carry; }
+    }
+    x[(size_t)(n - 1) * N] = carry;
+    // backward: U^-1, with the largest magnitude for the next scaling
+    double x2 = carry * U0[(size_t)(n - 1) * N + t];
+    x[(size_t)(n - 1) * N] = x2;
+    double x1 = (x[(size_t)(n - 2) * N] - U1[(size_t)(n - 2) * N + t] * x2) *
+                U0[(size_t)(n - 2) * N + t];
+    x[(size_t)(n - 2) * N] = x1;
+    double mx = fmax(fabs(x1), fabs(x2));
+    for (int i = n - 3; i >= 0; --i) {
+      const size_t ix = (size_t)i * N + t;
+      const double xi = (x[(size_t)i * N] - U1[ix] * x1 - U2[ix] * x2) * U0[ix];
+      x[(size_t)i * N] = xi;
+      mx = fmax(mx, fabs(xi));
+      x2 = x1; x1 = xi;
+    }
+    sc = 1.0 / mx;
+  }
+  double s2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double v = sc * x[(size_t)i * N];
+    s2 += v * v;
+  }
+  const double f = sc / sqrt(s2);
+  for (int i = 0; i < n; ++i) x[(size_t)i * N] *= f;
+}
+
+// grid (ceil(N / 4), nH), 256 threads: the wave of eigenvalue t acts if t
+// starts a cluster of two or more inside its block.
+__global__ void __launch_bounds__(256)
+mgs_kernel(int N, EigBufs E) {
+  const int hv = blockIdx.y, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= N) return;
+  const size_t o = (size_t)hv * N;
+  const int b0 = E.bnd[o * 2 + t], b1 = E.bnd[o * 2 + N + t];
+  const double* lam = E.lam + o;
+  const double gap = kClusterTol * E.bnorm[o + t];
+  if (!(t == b0 || lam[t] - lam[t - 1] >= gap)) return;   // not a leader
+  int c1 = t + 1;
+  while (c1 < b1 && lam[c1] - lam[c1 - 1] < gap) ++c1;
+  if (c1 - t < 2) return;
+  double* Z = E.A + (size_t)hv * N * N;
+  for (int jc = t + 1; jc < c1; ++jc) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = t; q < jc; ++q) {
+        double dt = 0.0;
+        for (int r = b0 + lane; r < b1; r += 64)
+          dt += Z[(size_t)r * N + jc] * Z[(size_t)r * N + q];
+        dt = wave_sum(dt);
+        for (int r = b0 + lane; r < b1; r += 64)
+          Z[(size_t)r * N + jc] -= dt * Z[(size_t)r * N + q];
+      }
+      double s2 = 0.0;
+      for (int r = b0 + lane; r < b1; r += 64) {
+        const double v = Z[(size_t)r * N + jc];
+        s2 += v * v;
+      }
+      s2 = wave_sum(s2);
+      // a vector that the projections annihilated cannot be trusted: NaN
+      // propagates to the caller's non-finite flag
+      const double f = s2 > 1e-24 ? 1.0 / sqrt(s2) : NAN;
+      for (int r = b0 + lane; r < b1; r += 64) Z[(size_t)r * N + jc] *= f;
+    }
+  }
+}
+
+// grid (ceil(N / 64), ceil(N / 64), nH), 256 threads: P = (Q Z)^2 by 64x64
+// tiles, 16-deep slices of the contraction through LDS, 4x4 per thread.
+__global__ void __launch_bounds__(256)
+psi_sq_kernel(int N, EigBufs E) {
+  const int hv = blockIdx.z;
+  const int i0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
+  const double* Qm = E.Q + (size_t)hv * N * N;
+  const double* Z = E.A + (size_t)hv * N * N;
+  double* P = E.P + (size_t)hv * N * N;
+  __shared__ double qs[16][65];   // qs[j][i]
+  __shared__ double zs[16][65];   // zs[j][k]
+  const int tid = threadIdx.x, ti = tid >> 4, tk = tid & 15;
+  double acc[4][4] = {};
+  for (int j0 = 0; j0 < N; j0 += 16) {
+    for (int u = tid; u < 16 * 64; u += 256) {
+      const int jj = u & 15, ii = u >> 4;   // Q[i0+ii][j0+jj]
+      const int gi = i0 + ii, gj = j0 + jj;
+      qs[jj][ii] = (gi < N && gj < N) ? Qm[(size_t)gi * N + gj] : 0.0;
+      const int kk = u & 63, jz = u >> 6;   // Z[j0+jz][k0+kk]
+      const int zj = j0 + jz, zk = k0 + kk;
+      zs[jz][kk] = (zj < N && zk < N) ? Z[(size_t)zj * N + zk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      double a[4], b[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) { a[x] = qs[jj][ti + 16 * x]; b[x] = zs[jj][tk + 16 * x]; }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int gi = i0 + ti + 16 * x, gk = k0 + tk + 16 * y;
+      if (gi < N && gk < N) P[(size_t)gi * N + gk] = acc[x][y] * acc[x][y];
+    }
+}
+
+// grid (ceil(N / 64), ceil(B / 16)), 256 threads: rows [i0, i0+64) of the
+// matrices [b0, b0+16).  Matrices of one tile that belong to different h
+// vectors are done in turns (one per distinct h vector).  Thread: row
+// i0 + (tid & 63), matrices b0 + 4 (tid >> 6) + {0..3}.
+__global__ void __launch_bounds__(256)
+expand_kernel(const MatDesc* __restrict__ descs, int B, int N, EigBufs E,
+              double* __restrict__ dg) {
+  const int i0 = blockIdx.x * 64, bt0 = blockIdx.y * 16;
+  const int tid = threadIdx.x, il = tid & 63, bq = tid >> 6;
+  __shared__ double ps[16][65];       // ps[k][i]
+  __shared__ double wr[16][17], wi[16][17];   // [b][k]
+  __shared__ int hvs[16];
+  __shared__ double zr_s[16], zi_s[16];
+  if (tid < 16) {
+    const int b = bt0 + tid;
+    if (b < B) {
+      const MatDesc m = descs[b];
+      hvs[tid] = m.hoff / N; zr_s[tid] = m.zr; zi_s[tid] = m.zi;
+    } else {
+      hvs[tid] = -1; zr_s[tid] = 0.0; zi_s[tid] = 0.0;
+    }
+  }
+  __syncthreads();
+  unsigned done = 0;   // tile members finished (uniform across the group)
+  for (int b = 0; b < 16; ++b)
+    if (hvs[b] < 0) done |= 1u << b;
+  while (done != 0xFFFFu) {
+    const int first = __builtin_ctz(~done);
+    const int hv = hvs[first];
+    unsigned mine = 0;
+    for (int b = 0; b < 16; ++b)
+      if (!(done >> b & 1) && hvs[b] == hv) mine |= 1u << b;
+    const double* P = E.P + (size_t)hv * N * N;
+    const double* lam = E.lam + (size_t)hv * N;
+    double ar[4] = {}, ai[4] = {};
+    for (int k0 = 0; k0 < N; k0 += 16) {
+      for (int u = tid; u < 16 * 64; u += 256) {
+        const int kk = u & 15, ii = u >> 4;
+        const int gi = i0 + ii, gk = k0 + kk;
+        ps[kk][ii] = (gi < N && gk < N) ? P[(size_t)gi * N + gk] : 0.0;
+      }
+      {
+        const int b = tid >> 4, kk = tid & 15, gk = k0 + kk;
+        double re = 0.0, im = 0.0;
+        if ((mine >> b & 1) && gk < N) {
+          const double dr = zr_s[b] - lam[gk], di = zi_s[b];
+          const double den = 1.0 / (dr * dr + di * di);
+          re = dr * den; im = -di * den;
+        }
+        wr[b][kk] = re; wi[b][kk] = im;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const double p = ps[kk][il];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          ar[x] = fma(p, wr[4 * bq + x][kk], ar[x]);
+          ai[x] = fma(p, wi[4 * bq + x][kk], ai[x]);
+        }
+      }
+      __syncthreads();
+    }
+    const int gi = i0 + il;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int bl = 4 * bq + x;
+      if ((mine >> bl & 1) && gi < N) {
+        double* o = dg + ((size_t)(bt0 + bl) * N + gi) * 2;
+        o[0] = ar[x]; o[1] = ai[x];
+      }
+    }
+    done |= mine;
+  }
+}
+
+// grid (B), 64 threads
+__global__ void __launch_bounds__(64)
+lad_kernel(const MatDesc* __restrict__ descs, int N, EigBufs E,
+           double* __restrict__ lad, double* __restrict__ growth) {
+  const int b = blockIdx.x;
+  const MatDesc m = descs[b];
+  const double* lam = E.lam + (size_t)(m.hoff / N) * N;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < N; k += 64) {
+    const double dr = m.zr - lam[k];
+    s += log(dr * dr + m.zi * m.zi);
+  }
+  s = wave_sum(s);
+  if (threadIdx.x == 0) {
+    if (lad) lad[b] = 0.5 * s;
+    if (growth) growth[b] = 1.0;
+  }
+}
+
+hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
+                          const double* hbuf, int B, int N, int L, double* lad,
+                          double* dg, double* growth, void* fact,
+                          hipStream_t st) {
+  if (nH <= 0 || !probs || !fact) return hipErrorInvalidValue;
+  EigBufs E = carve_eig(fact, N, nH);
+  mark_begin(K_TRIDIAG, st);
+  hipLaunchKernelGGL(eig_init_kernel, dim3(N, nH), dim3(256), 0, st, probs,
+                     hbuf, N, L, E);
+  const int nrow = (N + kRowsPerWg - 1) / kRowsPerWg;
+  for (int j = 0; j < N; ++j)
+    hipLaunchKernelGGL(hh_step_kernel, dim3(nrow, nH), dim3(256),
+                       sizeof(double) * 3 * N, st, N, j, E);
+  mark_end(K_TRIDIAG, st);
+  mark_begin(K_SPECTRUM, st);
+  hipLaunchKernelGGL(bisect_kernel, dim3((N + 3) / 4, nH), dim3(256),
+                     sizeof(double) * 2 * N, st, N, E);
+  hipLaunchKernelGGL(invit_kernel, dim3((N + 63) / 64, nH), dim3(64), 0, st,
+                     N, E);
+  hipLaunchKernelGGL(mgs_kernel, dim3((N + 3) / 4, nH), dim3(256), 0, st, N,
+                     E);
+  hipLaunchKernelGGL(psi_sq_kernel, dim3((N + 63) / 64, (N + 63) / 64, nH),
+                     dim3(256), 0, st, N, E);
+  mark_end(K_SPECTRUM, st);
+  mark_begin(K_EXPAND, st);
+  if (dg)
+    hipLaunchKernelGGL(expand_kernel, dim3((N + 63) / 64, (B + 15) / 16),
+                       dim3(256), 0, st, descs, B, N, E, dg);
+  hipLaunchKernelGGL(lad_kernel, dim3(B), dim3(64), 0, st, descs, N, E, lad,
+                     growth);
+  mark_end(K_EXPAND, st);
+  return hipGetLastError();
+}
+
+}  // namespace sca

@@ -64,7 +64,8 @@ sca_status validate_params(const sca_params* p) {
     return fail(SCA_EINVAL, "n_max=%d: must be in [1, %d]", p->n_max, kMaxNmax);
   if (p->precision != SCA_FP64 && p->precision != SCA_FP32_REFINED)
     return fail(SCA_EINVAL, "precision=%d: unknown", p->precision);
-  if (p->factor != SCA_FACTOR_LU && p->factor != SCA_FACTOR_LDLT)
+  if (p->factor != SCA_FACTOR_LU && p->factor != SCA_FACTOR_LDLT &&
+      p->factor != SCA_FACTOR_EIGH)
     return fail(SCA_EINVAL, "factor=%d: unknown", p->factor);
   if (p->tail != SCA_TAIL_NONE && p->tail != SCA_TAIL_MOMENTS)
     return fail(SCA_EINVAL, "tail=%d: unknown", p->tail);
@@ -84,7 +85,8 @@ sca_status validate_params(const sca_params* p) {
 
 int route_of(const sca_params* p) {
   return (p->precision == SCA_FP32_REFINED ? kModeFp32 : 0) |
-         (p->factor == SCA_FACTOR_LDLT ? kModeSym : 0);
+         (p->factor == SCA_FACTOR_LDLT ? kModeSym : 0) |
+         (p->factor == SCA_FACTOR_EIGH ? kModeEig : 0);
 }
 
 sca_status check_device_ptr(int device, const void* ptr, const char* name,
@@ -158,7 +160,7 @@ hipError_t enqueue_pass(const Carve& c, int nprob, int L, int B,
     e = launch_tail(c.probs, nprob, N, c.hbuf, c.mom, c.tsum, st);
   if (e == hipSuccess)
     e = factor_batch(c.descs, c.hbuf, B, N, L, precision, c.lad, c.dg,
-                     c.growth, c.fact, st);
+                     c.growth, c.fact, st, c.probs, 2 * nprob);
   if (e == hipSuccess)
     e = launch_reduce(c.probs, nprob, N, c.lad, c.dg, c.growth, c.stats, adam,
                       c.rws, c.mom, c.tsum, st, c.hmc_on);
@@ -677,7 +679,7 @@ sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
   HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
   HIP_TRY(launch_shift_descs(z, n_z, p->t, 0, N, c.descs, st));
   HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, p->L, route_of(p), logabsdet,
-                       diag, c.growth, c.fact, st));
+                       diag, c.growth, c.fact, st, c.probs, 2));
   HIP_TRY(hipStreamSynchronize(st));
   return SCA_OK;
 }
@@ -712,7 +714,7 @@ sca_status sca_dos(sca_ctx* ctx, const sca_params* p, const double* phi,
   HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
   HIP_TRY(launch_shift_descs(zbuf, n_w, p->t, 0, N, c.descs, st));
   HIP_TRY(factor_batch(c.descs, c.hbuf, B, N, p->L, route_of(p), c.lad, c.dg,
-                       c.growth, c.fact, st));
+                       c.growth, c.fact, st, c.probs, 2));
   HIP_TRY(launch_dos_reduce(c.dg, n_w, N, rho, st));
   HIP_TRY(hipStreamSynchronize(st));
   return SCA_OK;
@@ -722,6 +724,7 @@ size_t sca_factor_bytes(const sca_params* p) {
   std::string saved = g_err;
   if (validate_params(p) != SCA_OK) return 0;
   g_err = saved;
+  if (p->factor == SCA_FACTOR_EIGH) return 0;   // no factors to keep
   const int N = p->L * p->L, B = 2 * p->n_max;
   return autograd_factor_bytes(N, B, route_of(p));
 }
@@ -730,6 +733,9 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
                          void* factors, double* omega2) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
+  if (p->factor == SCA_FACTOR_EIGH)
+    return fail(SCA_EUNSUPPORTED, "the spectral route keeps no factors: use "
+                "sca_potential / sca_grad");
   DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
@@ -778,6 +784,9 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
                                  double* grad) {
   sca_status s = begin_call(ctx, p);
   if (s) return s;
+  if (p->factor == SCA_FACTOR_EIGH)
+    return fail(SCA_EUNSUPPORTED, "the spectral route keeps no factors: use "
+                "sca_grad");
   DeviceGuard g(ctx, ctx->device);
   if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;

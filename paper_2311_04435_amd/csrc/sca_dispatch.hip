@@ -9,6 +9,8 @@
 //   FP32 refined, N <= 2304: blocked complex64 LU and U^-1 / L^-1, the
 //              product X = W V, then the FP64 Newton diagonal and the
 //              refined log-determinant.
+//   spectral (FP64), any N: one eigendecomposition per h vector, every
+//              matrix from the spectrum (k_eig.hip).
 #include "sca_blocked.h"
 #include "sca_common.h"
 #include "sca_kernels.h"
@@ -24,6 +26,7 @@ bool sym_mode(int mode) { return (mode & kModeSym) != 0; }
 }  // namespace
 
 bool path_supported(int N, int mode) {
+  if (mode == kModeEig) return N >= 1;
   if (N < 1 || mode < 0 || mode > 3) return false;
   if (N <= kSmallMax) return true;
   if (fp32_mode(mode) && sym_mode(mode)) return false;
@@ -44,7 +47,8 @@ size_t sym_extra_bytes(const BlockedPlan& p, int B) {
 
 }  // namespace
 
-size_t factor_workspace_bytes(int N, int B, int mode) {
+size_t factor_workspace_bytes(int N, int B, int mode, int nH) {
+  if (mode == kModeEig) return eig_workspace_bytes(N, nH);
   if (N <= kSmallMax) return 0;
   const BlockedPlan p = blocked_plan(N, fp32_mode(mode));
   if (p.cfg < 0) return 0;
@@ -121,8 +125,12 @@ hipError_t sym_batch(const BlockedPlan& p, const MatDesc* descs,
 
 hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
                         int L, int mode, double* lad, double* dg,
-                        double* growth, void* fact, hipStream_t st) {
+                        double* growth, void* fact, hipStream_t st,
+                        const ProbDesc* probs, int nH) {
   if (B <= 0) return hipSuccess;
+  if (mode == kModeEig)
+    return spectral_batch(probs, nH, descs, hbuf, B, N, L, lad, dg, growth,
+                          fact, st);
   if (N <= kSmallMax)
     return launch_small_factor(descs, hbuf, B, N, L, lad, dg, growth, st);
   const BlockedPlan p = blocked_plan(N, fp32_mode(mode));

@@ -21,6 +21,9 @@ enum KernelClass {
   K_SYMDIAG = 10,   // symmetric route: diagonal of A^-1
   K_FALLBACK = 11,  // symmetric route: pivoted LU of flagged matrices
   K_TAIL = 12,      // Matsubara tail: moments of H and frequency sums
+  K_TRIDIAG = 13,   // spectral route: Householder tridiagonalisation
+  K_SPECTRUM = 14,  // spectral route: eigenvalues, eigenvectors, psi^2
+  K_EXPAND = 15,    // spectral route: per-matrix terms from the spectrum
   K_COUNT = 16
 };
 

@@ -13,23 +13,38 @@ constexpr int kMaxNmax = 1 << 16;   // Matsubara frequencies per spin
 constexpr int kMaxShifts = 1 << 20; // shifts per sca_dos / sca_shifted_terms
 
 // Route code of a parameter point (the `mode` argument of the functions
-// below): bit 0 = FP32 refined, bit 1 = symmetric L D L^T.
+// below): bit 0 = FP32 refined, bit 1 = symmetric L D L^T, bit 2 = spectral
+// (one eigendecomposition per h vector instead of a factorisation per
+// matrix; FP64 only).
 constexpr int kModeFp32 = 1;
 constexpr int kModeSym = 2;
+constexpr int kModeEig = 4;
 
 // Whether a factorisation path exists for N sites on route `mode`.
 bool path_supported(int N, int mode);
 
 // Scratch (bytes) the factorisation of B matrices of N sites needs beyond
-// the per-matrix outputs (0 for the fused small path).
-size_t factor_workspace_bytes(int N, int B, int mode);
+// the per-matrix outputs (0 for the fused small path).  The spectral route's
+// scratch depends on the number nH of h vectors instead of B.
+size_t factor_workspace_bytes(int N, int B, int mode, int nH = 2);
 
 // ln|det A_b| -> lad[b], diag(A_b^-1) -> dg[b][N][2] (re, im), pivot growth
 // -> growth[b], for the B matrices described by descs.  `fact` is the
-// scratch of factor_workspace_bytes(N, B, mode) bytes.
+// scratch of factor_workspace_bytes(N, B, mode, nH) bytes.  The spectral
+// route also needs the problems (probs: hopping of problem hv / 2) and the
+// number nH of h vectors in hbuf (vector hv at hbuf + hv N).
 hipError_t factor_batch(const MatDesc* descs, const double* hbuf, int B, int N,
                         int L, int mode, double* lad, double* dg,
-                        double* growth, void* fact, hipStream_t st);
+                        double* growth, void* fact, hipStream_t st,
+                        const ProbDesc* probs = nullptr, int nH = 0);
+
+// Spectral route (k_eig.hip): the outputs of factor_batch from one
+// eigendecomposition per h vector; growth is 1 (no pivoting).
+size_t eig_workspace_bytes(int N, int nH);
+hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
+                          const double* hbuf, int B, int N, int L, double* lad,
+                          double* dg, double* growth, void* fact,
+                          hipStream_t st);
 
 // Autograd split of factor_batch.  The forward writes lad and growth and
 // keeps in `fact` (and, for the fused small path and the FP32 route, in dg)

@@ -104,7 +104,7 @@ struct Group {
 size_t group_bytes(int N, int M, int precision, int cap) {
   const int B = 2 * M * cap;
   return carve(nullptr, cap, N, B, precision, true, true,
-               factor_workspace_bytes(N, B, precision)).total;
+               factor_workspace_bytes(N, B, precision, 2 * cap)).total;
 }
 
 }  // namespace
@@ -187,7 +187,7 @@ sca_status new_group(sca_server* s, const Request* r, Group** out) {
   SCA_HIP_TRY(hipHostMalloc((void**)&g->pin_stats, sizeof(ProbStats) * cap,
                             hipHostMallocDefault));
   g->c = carve(static_cast<char*>(g->ws), cap, N, 2 * M * cap, prec, true,
-               true, factor_workspace_bytes(N, 2 * M * cap, prec));
+               true, factor_workspace_bytes(N, 2 * M * cap, prec, 2 * cap));
   s->used += bytes;
   *out = g.get();
   s->groups.push_back(std::move(g));

@@ -47,7 +47,7 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [dict(L=3), dict(L=0), dict(L=66), dict(n_max=0),
                                  dict(U=0.0), dict(U=-1.0), dict(T=0.0),
                                  dict(T=float("nan")), dict(t=float("inf")),
-                                 dict(precision=7), dict(factor=2),
+                                 dict(precision=7), dict(factor=3),
                                  dict(tail=2), dict(reserved=1)])
 def test_invalid_params_rejected_without_device(bad):
     from paper_2311_04435_amd import _lib
@@ -75,6 +75,20 @@ def test_footprint_grows_with_problem():
     # at least the per-matrix outputs: 2M matrices x N complex diagonal
     assert b >= 2 * 256 * 16 * 16
     assert _lib.lib.sca_factor_bytes(C.byref(_params())) >= 2 * 256 * 16 * 16
+
+
+def test_spectral_route_footprint():
+    """SCA_FACTOR_EIGH: scratch of a few N^2 per spin instead of a factor
+    per matrix; FP64 only; no factor buffer."""
+    from paper_2311_04435_amd import _lib
+    f = lambda **kw: _lib.lib.sca_footprint_bytes(C.byref(_params(**kw)))
+    lu, eig = f(L=20, n_max=512), f(L=20, n_max=512, factor=2)
+    assert 0 < eig < lu / 20
+    # eigenvectors, reflectors and psi^2 of both spins at least
+    assert eig >= 3 * 2 * 400 * 400 * 8
+    assert f(L=20, n_max=512, factor=2, precision=1) == 0
+    assert f(L=2, n_max=8, factor=2) > 0
+    assert _lib.lib.sca_factor_bytes(C.byref(_params(factor=2))) == 0
 
 
 def test_create_without_gpu_reports_device_error():
