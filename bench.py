@@ -28,7 +28,12 @@ Prints one JSON line.  Besides the contract fields it carries
   serving       served solves/s and p50/p99 latency of a Poisson stream of
                 mixed requests through the request server, next to the
                 one-at-a-time FIFO baseline on the same GPU;
-  serving_tail  the same stream with the Matsubara tail by moments.
+  serving_tail  the same stream with the Matsubara tail by moments;
+  spectral      the spectral route (factor eigh: one eigendecomposition of
+                H per spin, every frequency from the spectrum) on the
+                workload with its per-class times, on the 48x48 ionic
+                lattice, and the FP32-refined factorisation route on that
+                lattice for comparison.
 """
 from __future__ import annotations
 
@@ -96,6 +101,9 @@ def kernel_work(kind: str, N: int, B: int):
         return B * 8.0 * N * N, "byte", "hbm"
     if kind == "reduce":      # reads diag(A^-1) of every matrix
         return B * 16.0 * N, "byte", "hbm"
+    if kind == "tridiag":     # spectral route, both spins: Householder
+        # reduction (4/3) N^3 and the accumulated reflectors (4/3) N^3
+        return 2 * 8.0 / 3.0 * n3, "flop", "alu"
     return None
 
 
@@ -235,7 +243,7 @@ def route_line(sca, name, prec, factor, steps, warmup, tail=False):
         if unit == "flop":
             peak = PEAK["fp32" if prec == "fp32r" else "fp64"]
             ach = amount / avg_s / 1e12
-            out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": ach,
+            out["roofline"] = {"bound": bound, "kernel": dom, "achieved": ach,
                                "peak": peak, "unit": "TFLOP/s",
                                "frac": ach / peak,
                                "traffic": None if tail else
@@ -320,6 +328,8 @@ def main():
     ap.add_argument("--no-l32", action="store_true")
     ap.add_argument("--no-tail", action="store_true",
                     help="skip the Matsubara-tail lines")
+    ap.add_argument("--no-spectral", action="store_true",
+                    help="skip the spectral-route lines (factor eigh)")
     ap.add_argument("--no-hmc", action="store_true",
                     help="skip the Hybrid Monte Carlo line")
     ap.add_argument("--no-symmetric", action="store_true",
@@ -451,6 +461,17 @@ def main():
         out["tail"] = [route_line(sca, args.workload, "fp64", f,
                                   max(args.steps, 20), args.warmup, tail=True)
                        for f in ("lu", "ldlt")]
+    if prec == "fp64" and not args.no_spectral:
+        # one eigendecomposition per spin instead of a factorisation per
+        # frequency: the same workload, and the 48x48 ionic lattice against
+        # its factorisation route (FP32 refined)
+        out["spectral"] = [
+            route_line(sca, args.workload, "fp64", "eigh",
+                       max(args.steps, 20), args.warmup),
+            workload_rate(sca, "ionic_48x48", "fp64", 5, 1, "eigh")]
+        if not args.no_l32:
+            out["spectral"].append(workload_rate(sca, "ionic_48x48", "fp32r",
+                                                 1, 1))
     if prec == "fp64" and not args.no_hmc:
         out["hmc"] = hmc_line(sca, args.workload)
     if args.serving_requests > 0:

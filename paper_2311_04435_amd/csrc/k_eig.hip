@@ -24,7 +24,7 @@
 //                      ten rounds.
 //   invit_kernel       one lane per eigenvalue: pivoted LU of T_blk - lambda,
 //                      three solves from a counter-hashed start vector.
-//   mgs_kernel         eigenvalues of one block closer than 1e-3 |T_blk| form
+//   mgs_kernel         eigenvalues of one block closer than 1e-4 |T_blk| form
 //                      a cluster; its vectors are orthonormalised (modified
 //                      Gram-Schmidt, two passes) in index order.
 //   psi_sq_kernel      P = (Q Z) o (Q Z) (tiled GEMM, squared in the epilogue)
@@ -45,7 +45,7 @@ constexpr int kRowsPerWg = 4;     // hh_step: one wave per row
 constexpr int kBisRounds = 10;    // 65^-10 of the Gershgorin width
 constexpr int kInvIters = 3;
 constexpr double kEps = DBL_EPSILON;
-constexpr double kClusterTol = 1e-3;
+constexpr double kClusterTol = 1e-4;
 constexpr double kSplitTol = 2.0;   // split where |e_i| <= kSplitTol eps |T|
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -158,6 +158,11 @@ eig_init_kernel(const ProbDesc* __restrict__ probs, const double* __restrict__ h
 // Column j of A_j is formed from the previous launch's copy of column j of
 // A_{j-1}; its entries below the diagonal give the reflector of column j
 // (v_{j+1} = 1, tau = (beta - alpha)/beta, beta = -sign(alpha) |x|).
+// Rows and columns below j+1 of A are never read again, so a wave keeps
+// only A[r][j+1 ..] of its row r > j (and Q[r][j ..]) in registers: lane
+// holds columns c0 + lane + 64 k, k < KM; every global load of the launch
+// is issued before the first reduction.
+template <int KM>
 __global__ void __launch_bounds__(256)
 hh_step_kernel(int N, int j, EigBufs E) {
   const int hv = blockIdx.y;
@@ -174,41 +179,58 @@ hh_step_kernel(int N, int j, EigBufs E) {
   __shared__ double red[4];
   const int cur = j & 1, prv = cur ^ 1;
   const bool pend = j > 0;
+  const bool rowA = r < N && r > j;    // A row of this wave still in play
+  const bool rowQ = pend && r < N;
+  double ar[KM], qr[KM];
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    const int ca = j + 1 + lane + 64 * k, cq = j + lane + 64 * k;
+    ar[k] = (rowA && ca < N) ? A[(size_t)r * N + ca] : 0.0;
+    qr[k] = (rowQ && cq < N) ? Q[(size_t)r * N + cq] : 0.0;
+  }
   double tp = 0.0;
   if (pend) {
     tp = taub[prv];
     const double* vp = vb + prv * N;
     const double* pp = vb + (2 + prv) * N;
+    const double* cp = vb + (4 + prv) * N;
     double s = 0.0;
     for (int c = j + tid; c < N; c += 256) {
       const double a = vp[c], b = pp[c];
-      sv[c] = a; sw[c] = b; s += a * b;
+      sv[c] = a; sw[c] = b; sx[c] = cp[c]; s += a * b;
     }
     s = block_sum(s, red);
     const double K = 0.5 * tp * s;
     for (int c = j + tid; c < N; c += 256) sw[c] -= K * sv[c];
-  }
-  __syncthreads();
-  // column j of A_j, rows [j, N)
-  if (!pend) {
-    for (int q = tid; q < N; q += 256) sx[q] = A[(size_t)q * N];
-  } else {
-    const double* cp = vb + (4 + prv) * N;
+    __syncthreads();
+    // column j of A_j, rows [j, N)
     const double wj = sw[j], vj = sv[j];
-    for (int q = j + tid; q < N; q += 256) sx[q] = cp[q] - sv[q] * wj - sw[q] * vj;
+    for (int q = j + tid; q < N; q += 256) sx[q] -= sv[q] * wj + sw[q] * vj;
+  } else {
+    for (int q = tid; q < N; q += 256) sx[q] = A[(size_t)q * N];
   }
-  // pending update of this wave's row
-  if (pend && r < N) {
-    if (r >= j) {
-      double* Ar = A + (size_t)r * N;
-      const double vr = sv[r], wr = sw[r];
-      for (int c = j + lane; c < N; c += 64) Ar[c] -= vr * sw[c] + wr * sv[c];
+  // pending update of this wave's rows (registers)
+  if (rowA && pend) {
+    const double vr = sv[r], wr = sw[r];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const int c = j + 1 + lane + 64 * k;
+      if (c < N) ar[k] -= vr * sw[c] + wr * sv[c];
     }
-    double* Qr = Q + (size_t)r * N;
+  }
+  if (rowQ) {
     double qv = 0.0;
-    for (int c = j + lane; c < N; c += 64) qv += Qr[c] * sv[c];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const int c = j + lane + 64 * k;
+      if (c < N) qv += qr[k] * sv[c];
+    }
     qv = wave_sum(qv) * tp;
-    for (int c = j + lane; c < N; c += 64) Qr[c] -= qv * sv[c];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const int c = j + lane + 64 * k;
+      if (c < N) Q[(size_t)r * N + c] = qr[k] - qv * sv[c];
+    }
   }
   __syncthreads();
   if (j == N - 1) {   // last diagonal entry; no reflector
@@ -242,15 +264,22 @@ hh_step_kernel(int N, int j, EigBufs E) {
     double* vn = vb + cur * N;
     for (int q = j + 1 + tid; q < N; q += 256) vn[q] = sx[q];
   }
-  // p = tau A_j v and the copy of column j+1 of A_j, rows of this wave
-  if (r < N && r >= j + 1) {
-    const double* Ar = A + (size_t)r * N;
+  // p = tau A_j v, the copy of column j+1 of A_j, and the row for the next
+  // launch (columns j+2 ..; column j+1 travels in the copy)
+  if (rowA) {
     double pr = 0.0;
-    for (int c = j + 1 + lane; c < N; c += 64) pr += Ar[c] * sx[c];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const int c = j + 1 + lane + 64 * k;
+      if (c < N) {
+        pr += ar[k] * sx[c];
+        if (c > j + 1) A[(size_t)r * N + c] = ar[k];
+      }
+    }
     pr = wave_sum(pr) * tau;
     if (lane == 0) {
       vb[(2 + cur) * N + r] = pr;
-      vb[(4 + cur) * N + r] = Ar[j + 1];
+      vb[(4 + cur) * N + r] = ar[0];
     }
   }
 }
@@ -263,6 +292,7 @@ __device__ inline int sturm_count(const double* __restrict__ d,
   double q = d[b0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   c += q < 0.0;
+#pragma unroll 4
   for (int i = b0 + 1; i < b1; ++i) {
     q = (d[i] - x) - e2[i - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
@@ -349,36 +379,41 @@ bisect_kernel(int N, EigBufs E) {
 // grid (ceil(N / 64), nH), 64 threads: lane = eigenvalue t.  Column t of Z
 // (stored over A) is zero outside the block of t; inside it the inverse
 // iteration with T_blk - lambda_t = P L U (partial pivoting; pivots below
-// eps |T_blk| raised to it).
+// eps |T_blk| raised to it).  Each solve is a serial chain per lane: d and e
+// come from LDS, and the factors and the right-hand side are loaded a group
+// of kG steps ahead of the stores of the current group.
+constexpr int kG = 8;
 __global__ void __launch_bounds__(64)
 invit_kernel(int N, EigBufs E) {
   const int hv = blockIdx.y;
   const int t = blockIdx.x * 64 + threadIdx.x;
-  if (t >= N) return;
   const size_t o = (size_t)hv * N;
-  const double* d = E.d + o;
-  const double* e = E.e + o;
-  double* Z = E.A + (size_t)hv * N * N;
+  extern __shared__ double sm[];
+  double* sd = sm;
+  double* se = sm + N;
+  for (int i = threadIdx.x; i < N; i += 64) { sd[i] = E.d[o + i]; se[i] = E.e[o + i]; }
+  __syncthreads();
+  if (t >= N) return;
+  double* __restrict__ Z = E.A + (size_t)hv * N * N;
   const size_t n2 = (size_t)N * N;
-  double* U0 = E.lu + (size_t)hv * 4 * n2;
-  double* U1 = U0 + n2;
-  double* U2 = U1 + n2;
-  double* Mm = U2 + n2;
-  unsigned char* Pv = E.piv + (size_t)hv * n2;
+  double* __restrict__ U0 = E.lu + (size_t)hv * 4 * n2;
+  double* __restrict__ U1 = U0 + n2;
+  double* __restrict__ U2 = U1 + n2;
+  double* __restrict__ Mm = U2 + n2;
+  unsigned char* __restrict__ Pv = E.piv + (size_t)hv * n2;
   const int b0 = E.bnd[o * 2 + t], b1 = E.bnd[o * 2 + N + t];
   const int n = b1 - b0;
   const double lam = E.lam[o + t], bn = E.bnorm[o + t];
   for (int q = 0; q < N; ++q)
     if (q < b0 || q >= b1) Z[(size_t)q * N + t] = 0.0;
   if (n == 1) { Z[(size_t)b0 * N + t] = 1.0; return; }
-  // the splits of the bisection (the block's own couplings are nonzero)
   const double tol = kEps * bn;
   // elimination; the current row holds (cd, cs) at columns (i, i+1)
-  double cd = d[b0] - lam, cs = e[b0];
+  double cd = sd[b0] - lam, cs = se[b0];
   for (int i = 0; i < n - 1; ++i) {
-    const double ci = e[b0 + i];
-    const double an = d[b0 + i + 1] - lam;
-    const double bnx = i + 1 < n - 1 ? e[b0 + i + 1] : 0.0;
+    const double ci = se[b0 + i];
+    const double an = sd[b0 + i + 1] - lam;
+    const double bnx = i + 1 < n - 1 ? se[b0 + i + 1] : 0.0;
     const bool pv = fabs(ci) > fabs(cd);
     double u0, u1, u2, m;
     if (pv) {
@@ -400,35 +435,80 @@ invit_kernel(int N, EigBufs E) {
   }
   if (fabs(cd) < tol) cd = cd >= 0.0 ? tol : -tol;
   U0[(size_t)(n - 1) * N + t] = 1.0 / cd;
-  double* x = Z + (size_t)b0 * N + t;   // x[i] at x[i * N]
+  double* __restrict__ x = Z + (size_t)b0 * N + t;   // x[i] at x[i * N]
+  const unsigned long long seed = (unsigned long long)t << 32;
+  const int nf = n - 1;   // forward steps
   double sc = 1.0;
   for (int it = 0; it < kInvIters; ++it) {
-    // forward: L^-1 P (sc * y), y = start vector on the first pass
-    double carry = it == 0 ? hash_uniform(((unsigned long long)t << 32) | 0u)
-                           : sc * x[0];
-    for (int i = 0; i < n - 1; ++i) {
-      const size_t ix = (size_t)i * N + t;
-      const double y = it == 0 ? hash_uniform(((unsigned long long)t << 32) |
-                                              (unsigned)(i + 1))
-                               : sc * x[(size_t)(i + 1) * N];
-      const double m = Mm[ix];
-      if (Pv[ix]) { x[(size_t)i * N] = y; carry = carry - m * y; }
-      else { x[(size_t)i * N] = carry; carry = y - m * carry; }
+    // forward: L^-1 P (sc y); y is the hashed start vector on the first pass
+    const bool first = it == 0;
+    double carry = first ? hash_uniform(seed) : sc * x[0];
+    double ya[kG] = {}, ma[kG] = {}, yb[kG] = {}, mb[kG] = {};
+    unsigned char pa[kG] = {}, pb[kG] = {};
+    auto load_f = [&](int i0, double* y, double* m, unsigned char* p) {
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int i = i0 + u;
+        if (i < nf) {
+          y[u] = first ? hash_uniform(seed | (unsigned)(i + 1))
+                       : x[(size_t)(i + 1) * N];
+          m[u] = Mm[(size_t)i * N + t];
+          p[u] = Pv[(size_t)i * N + t];
+        }
+      }
+    };
+    load_f(0, ya, ma, pa);
+    for (int i0 = 0; i0 < nf; i0 += kG) {
+      if (i0 + kG < nf) load_f(i0 + kG, yb, mb, pb);
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int i = i0 + u;
+        if (i < nf) {
+          const double y = first ? ya[u] : sc * ya[u];
+          double out;
+          if (pa[u]) { out = y; carry = carry - ma[u] * y; }
+          else { out = carry; carry = y - ma[u] * carry; }
+          x[(size_t)i * N] = out;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kG; ++u) { ya[u] = yb[u]; ma[u] = mb[u]; pa[u] = pb[u]; }
     }
-    x[(size_t)(n - 1) * N] = carry;
     // backward: U^-1, with the largest magnitude for the next scaling
-    double x2 = carry * U0[(size_t)(n - 1) * N + t];
-    x[(size_t)(n - 1) * N] = x2;
-    double x1 = (x[(size_t)(n - 2) * N] - U1[(size_t)(n - 2) * N + t] * x2) *
-                U0[(size_t)(n - 2) * N + t];
-    x[(size_t)(n - 2) * N] = x1;
+    double x2 = carry * U0[(size_t)nf * N + t];
+    x[(size_t)nf * N] = x2;
+    double x1 = (x[(size_t)(nf - 1) * N] - U1[(size_t)(nf - 1) * N + t] * x2) *
+                U0[(size_t)(nf - 1) * N + t];
+    x[(size_t)(nf - 1) * N] = x1;
     double mx = fmax(fabs(x1), fabs(x2));
-    for (int i = n - 3; i >= 0; --i) {
-      const size_t ix = (size_t)i * N + t;
-      const double xi = (x[(size_t)i * N] - U1[ix] * x1 - U2[ix] * x2) * U0[ix];
-      x[(size_t)i * N] = xi;
-      mx = fmax(mx, fabs(xi));
-      x2 = x1; x1 = xi;
+    double ra[kG] = {}, a0[kG] = {}, a1[kG] = {}, a2[kG] = {};
+    double rb[kG] = {}, c0[kG] = {}, c1[kG] = {}, c2[kG] = {};
+    auto load_b = [&](int i0, double* r, double* u0, double* u1, double* u2) {
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int i = i0 - u;
+        if (i >= 0) {
+          const size_t ix = (size_t)i * N + t;
+          r[u] = x[(size_t)i * N]; u0[u] = U0[ix]; u1[u] = U1[ix]; u2[u] = U2[ix];
+        }
+      }
+    };
+    const int top = nf - 2;   // first row of the general recurrence
+    if (top >= 0) load_b(top, ra, a0, a1, a2);
+    for (int i0 = top; i0 >= 0; i0 -= kG) {
+      if (i0 - kG >= 0) load_b(i0 - kG, rb, c0, c1, c2);
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int i = i0 - u;
+        if (i >= 0) {
+          const double xi = (ra[u] - a1[u] * x1 - a2[u] * x2) * a0[u];
+          x[(size_t)i * N] = xi;
+          mx = fmax(mx, fabs(xi));
+          x2 = x1; x1 = xi;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kG; ++u) { ra[u] = rb[u]; a0[u] = c0[u]; a1[u] = c1[u]; a2[u] = c2[u]; }
     }
     sc = 1.0 / mx;
   }
@@ -439,6 +519,115 @@ invit_kernel(int N, EigBufs E) {
   }
   const double f = sc / sqrt(s2);
   for (int i = 0; i < n; ++i) x[(size_t)i * N] *= f;
+}
+
+// grid (N, nH), 64 threads: one wave per eigenvalue t, for N up to
+// kInvLdsMax.  The same iteration as invit_kernel (identical arithmetic and
+// start vector), with the block of T, the factors and the iterate in LDS:
+// lane 0 runs the serial recurrences, the wave copies in and out.
+// Above this the LDS (57 N bytes) leaves too few waves per CU to cover the
+// chains' latency and the lane-per-eigenvalue kernel is faster (measured at
+// N = 1024 and 2304).
+constexpr int kInvLdsMax = 512;
+__host__ __device__ constexpr size_t invit_lds_bytes(int N) {
+  return sizeof(double) * 7 * (size_t)N + (size_t)N;
+}
+__global__ void __launch_bounds__(64)
+invit_lds_kernel(int N, EigBufs E) {
+  const int t = blockIdx.x, hv = blockIdx.y, lane = threadIdx.x;
+  const size_t o = (size_t)hv * N;
+  const int b0 = E.bnd[o * 2 + t], b1 = E.bnd[o * 2 + N + t];
+  const int n = b1 - b0;
+  double* Z = E.A + (size_t)hv * N * N;
+  for (int q = lane; q < N; q += 64)
+    if (q < b0 || q >= b1) Z[(size_t)q * N + t] = 0.0;
+  if (n == 1) {
+    if (lane == 0) Z[(size_t)b0 * N + t] = 1.0;
+    return;
+  }
+  extern __shared__ double sm[];
+  double* __restrict__ sd = sm;
+  double* __restrict__ se = sd + n;
+  double* __restrict__ U0 = se + n;
+  double* __restrict__ U1 = U0 + n;
+  double* __restrict__ U2 = U1 + n;
+  double* __restrict__ Mm = U2 + n;
+  double* __restrict__ x = Mm + n;
+  unsigned char* __restrict__ Pv = reinterpret_cast<unsigned char*>(x + n);
+  __shared__ double sc_s;
+  const double lam = E.lam[o + t], bn = E.bnorm[o + t];
+  const unsigned long long seed = (unsigned long long)t << 32;
+  for (int i = lane; i < n; i += 64) {
+    sd[i] = E.d[o + b0 + i];
+    se[i] = E.e[o + b0 + i];
+    x[i] = hash_uniform(seed | (unsigned)i);
+  }
+  __syncthreads();
+  if (lane == 0) {
+    const double tol = kEps * bn;
+    double cd = sd[0] - lam, cs = se[0];
+#pragma unroll 2
+    for (int i = 0; i < n - 1; ++i) {
+      const double ci = se[i];
+      const double an = sd[i + 1] - lam;
+      const double bnx = i + 1 < n - 1 ? se[i + 1] : 0.0;
+      const bool pv = fabs(ci) > fabs(cd);
+      double u0, u1, u2, m;
+      if (pv) {
+        u0 = ci; u1 = an; u2 = bnx;
+        m = cd / ci;
+        const double ncd = cs - m * an;
+        cs = -m * bnx;
+        cd = ncd;
+      } else {
+        if (cd == 0.0) cd = tol;
+        u0 = cd; u1 = cs; u2 = 0.0;
+        m = ci / cd;
+        cd = an - m * cs;
+        cs = bnx;
+      }
+      if (fabs(u0) < tol) u0 = u0 >= 0.0 ? tol : -tol;
+      U0[i] = 1.0 / u0; U1[i] = u1; U2[i] = u2; Mm[i] = m; Pv[i] = pv;
+    }
+    if (fabs(cd) < tol) cd = cd >= 0.0 ? tol : -tol;
+    U0[n - 1] = 1.0 / cd;
+    const int nf = n - 1;
+    double sc = 1.0;
+    for (int it = 0; it < kInvIters; ++it) {
+      double carry = sc * x[0];
+#pragma unroll 4
+      for (int i = 0; i < nf; ++i) {
+        const double y = sc * x[i + 1];
+        const double m = Mm[i];
+        if (Pv[i]) { x[i] = y; carry = carry - m * y; }
+        else { x[i] = carry; carry = y - m * carry; }
+      }
+      double x2 = carry * U0[nf];
+      x[nf] = x2;
+      double x1 = (x[nf - 1] - U1[nf - 1] * x2) * U0[nf - 1];
+      x[nf - 1] = x1;
+      double mx = fmax(fabs(x1), fabs(x2));
+#pragma unroll 4
+      for (int i = nf - 2; i >= 0; --i) {
+        const double xi = (x[i] - U1[i] * x1 - U2[i] * x2) * U0[i];
+        x[i] = xi;
+        mx = fmax(mx, fabs(xi));
+        x2 = x1; x1 = xi;
+      }
+      sc = 1.0 / mx;
+    }
+    sc_s = sc;
+  }
+  __syncthreads();
+  const double sc = sc_s;
+  double s2 = 0.0;
+  for (int i = lane; i < n; i += 64) {
+    const double v = sc * x[i];
+    s2 += v * v;
+  }
+  s2 = wave_sum(s2);
+  const double f = sc / sqrt(s2);
+  for (int i = lane; i < n; i += 64) Z[(size_t)(b0 + i) * N + t] = x[i] * f;
 }
 
 // grid (ceil(N / 4), nH), 256 threads: the wave of eigenvalue t acts if t
@@ -630,15 +819,25 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
   hipLaunchKernelGGL(eig_init_kernel, dim3(N, nH), dim3(256), 0, st, probs,
                      hbuf, N, L, E);
   const int nrow = (N + kRowsPerWg - 1) / kRowsPerWg;
+  auto kern = N <= 512 ? hh_step_kernel<8> : N <= 1024 ? hh_step_kernel<16>
+            : N <= 2560 ? hh_step_kernel<40> : hh_step_kernel<64>;
   for (int j = 0; j < N; ++j)
-    hipLaunchKernelGGL(hh_step_kernel, dim3(nrow, nH), dim3(256),
+    hipLaunchKernelGGL(kern, dim3(nrow, nH), dim3(256),
                        sizeof(double) * 3 * N, st, N, j, E);
   mark_end(K_TRIDIAG, st);
   mark_begin(K_SPECTRUM, st);
   hipLaunchKernelGGL(bisect_kernel, dim3((N + 3) / 4, nH), dim3(256),
                      sizeof(double) * 2 * N, st, N, E);
-  hipLaunchKernelGGL(invit_kernel, dim3((N + 63) / 64, nH), dim3(64), 0, st,
-                     N, E);
+  if (N <= kInvLdsMax) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(invit_lds_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)invit_lds_bytes(N));
+    hipLaunchKernelGGL(invit_lds_kernel, dim3(N, nH), dim3(64),
+                       invit_lds_bytes(N), st, N, E);
+  } else {
+    hipLaunchKernelGGL(invit_kernel, dim3((N + 63) / 64, nH), dim3(64),
+                       sizeof(double) * 2 * N, st, N, E);
+  }
   hipLaunchKernelGGL(mgs_kernel, dim3((N + 3) / 4, nH), dim3(256), 0, st, N,
                      E);
   hipLaunchKernelGGL(psi_sq_kernel, dim3((N + 63) / 64, (N + 63) / 64, nH),
