@@ -415,11 +415,14 @@ def main():
         if unit == "flop":
             peak = PEAK["fp32" if prec == "fp32r" else "fp64"]
             achieved = amount / avg_s / 1e12
-            roof = {"bound": "mfma", "kernel": dom, "achieved": achieved,
+            roof = {"bound": bound, "kernel": dom, "achieved": achieved,
                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                     "traffic": measured_traffic(dom, args.workload, prec,
                                                 args.factor),
-                    "work_per_launch": f"{B} matrices x {amount / B:.4g} flop"}
+                    "work_per_launch": (
+                        f"2 spins x (8/3) N^3 = {amount:.4g} flop in N "
+                        f"dependent launches" if dom == "tridiag" else
+                        f"{B} matrices x {amount / B:.4g} flop")}
         else:
             achieved = amount / avg_s / 1e9
             roof = {"bound": "hbm", "kernel": dom, "achieved": achieved,
