@@ -202,6 +202,34 @@ def test_eigh_c2_trajectory_2000_steps(sca):
     assert res["max_pivot_growth"] == 1.0
 
 
+def test_eigh_c5_48x48(sca):
+    """The 48x48 ionic lattice on the spectral route against the oracle's
+    stored run (tests/golden/make_c5_trajectory.py): phi after 20 ADAM
+    steps, and at the oracle's phi after 1000 steps the gradient, Omega~
+    and the DOS."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "c5_trajectory_48x48.json")
+    with open(path) as f:
+        gold = json.load(f)
+    wl = synth.WORKLOADS["ionic_48x48"]
+    p = sca.Params.from_dict(wl["params"], factor="eigh")
+    phi0 = synth.make_phi0(48, wl["phi0"])
+    phi, m, v, res = sca.adam_solve(p, cuda(phi0), 20, final_eval=False)
+    ref = np.array(gold["phi20"])
+    e20 = np.max(np.abs(phi.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    phi_f = np.array(gold["phi1000"])
+    g, o2 = sca.grad(p, cuda(phi_f))
+    e_g = grad_err(g.cpu().numpy(), np.array(gold["grad"]), phi_f, p.U)
+    e_om = abs(o2[1].item() - gold["omega_tilde"]) / abs(gold["omega_tilde"])
+    rho = sca.dos(p, cuda(phi_f), cuda(gold["dos_w"]), gold["dos_eta"])
+    e_dos = rel_inf(rho.cpu().numpy(), np.array(gold["dos"]))
+    print(f"48x48 eigh: phi@20 {e20:.2e}; at phi@1000: grad {e_g:.2e}  "
+          f"Omega~ {e_om:.2e}  DOS {e_dos:.2e}")
+    assert e20 < 1e-10 and e_g < 1e-10 and e_om < 1e-10 and e_dos < 1e-10
+
+
 def test_eigh_hmc_chain(sca):
     N, L = 100, 10
     n_traj, n_leap, eps = 5, 6, 0.03

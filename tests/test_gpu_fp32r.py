@@ -162,3 +162,31 @@ def test_fp32r_c2_trajectory_2000_steps(sca):
     e_om = abs(res["omega_tilde"] - gold["omega_tilde"]) / abs(gold["omega_tilde"])
     print(f"fp32r 2000 steps: phi {e:.2e}  |phi| {e_af:.1e}  Omega~ {e_om:.1e}")
     assert e < TOL and e_af < TOL and e_om < TOL
+
+
+def test_c5_trajectory_48x48_first_20_steps(sca):
+    """The 48x48 ionic lattice (N = 2304, the largest workload): the first 20
+    ADAM steps of the refined-FP32 route against the oracle's trajectory
+    stored by tests/golden/make_c5_trajectory.py."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "c5_trajectory_48x48.json")
+    with open(path) as f:
+        gold = json.load(f)
+    wl = synth.WORKLOADS["ionic_48x48"]
+    p = sca.Params.from_dict(wl["params"], precision="fp32r")
+    phi0 = synth.make_phi0(48, wl["phi0"])
+    phi, m, v, res = sca.adam_solve(p, cuda(phi0), 20, final_eval=False)
+    ref = np.array(gold["phi20"])
+    e = np.max(np.abs(phi.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    # the converged state after 1000 oracle steps: gradient and Omega~ there
+    phi_f = np.array(gold["phi1000"])
+    g, o2 = sca.grad(p, cuda(phi_f))
+    gr = np.array(gold["grad"])
+    e_g = np.max(np.abs(g.cpu().numpy() - gr)) / max(np.max(np.abs(gr)),
+                                                     2 * np.max(np.abs(phi_f)) / p.U)
+    e_om = abs(o2[1].item() - gold["omega_tilde"]) / abs(gold["omega_tilde"])
+    print(f"48x48 fp32r: phi@20 err {e:.2e}; at phi@1000 grad err {e_g:.2e}, "
+          f"Omega~ err {e_om:.2e}")
+    assert e < TOL_GRAD and e_g < TOL_GRAD and e_om < TOL_GRAD
