@@ -11,14 +11,15 @@
 // The eigendecomposition follows the Householder / bisection / inverse
 // iteration scheme (Golub & Van Loan, Sec. 8.3-8.4; LAPACK's dsytrd, dstebz,
 // dstein describe the same steps):
-//   eig_init_kernel    dense H and Q = I per h vector
+//   eig_init_kernel    dense H per h vector
 //   hh_step_kernel     one launch per column j: the pending reflector of
 //                      column j-1 is applied to the trailing block of the
-//                      workgroup's rows (and to Q); column j is formed from
-//                      the previous launch's copy, its reflector built
-//                      (redundantly in every workgroup) and p = tau A v of
-//                      the workgroup's rows written for the next launch.
-//                      Q H Q^T-form: H = Q T Q^T, T tridiagonal (d, e).
+//                      workgroup's rows; column j is formed from the
+//                      previous launch's copy, its reflector built
+//                      (redundantly in every workgroup) and kept (V, tau),
+//                      and p = tau A v of the workgroup's rows written for
+//                      the next launch.  H = Q T Q^T, Q = H_0 H_1 .. H_{N-2},
+//                      T tridiagonal (d, e).
 //   bisect_kernel      T splits where |e_i| <= 2 eps |T|; one wave per
 //                      eigenvalue: 64 Sturm counts per round (65-section),
 //                      ten rounds.
@@ -27,8 +28,12 @@
 //   mgs_kernel         eigenvalues of one block closer than 1e-4 |T_blk| form
 //                      a cluster; its vectors are orthonormalised (modified
 //                      Gram-Schmidt, two passes) in index order.
-//   psi_sq_kernel      P = (Q Z) o (Q Z) (tiled GEMM, squared in the epilogue)
-//   expand_kernel      dg[b][i] = sum_k P_ik / (z_b - lambda_k)
+//   wy_t_kernel        compact WY factor T of each block of 32 reflectors:
+//                      H_j0 .. H_j0+31 = I - V T V^T (Schreiber & Van Loan)
+//   wy_apply_kernel    psi = Q Z in place: the blocks applied to Z from the
+//                      last to the first, each workgroup on its own slice
+//                      of 16 columns (no dependency between workgroups)
+//   expand_kernel      dg[b][i] = sum_k psi_k(i)^2 / (z_b - lambda_k)
 //   lad_kernel         lad[b] = sum_k ln|z_b - lambda_k|, growth[b] = 1
 #include <float.h>
 #include <math.h>
@@ -42,6 +47,8 @@ namespace sca {
 namespace {
 
 constexpr int kRowsPerWg = 4;     // hh_step: one wave per row
+constexpr int kWy = 32;           // reflectors per compact WY block
+constexpr int kWyCols = 16;       // columns of Z per back-transform workgroup
 constexpr int kBisRounds = 10;    // 65^-10 of the Gershgorin width
 constexpr int kInvIters = 3;
 constexpr double kEps = DBL_EPSILON;
@@ -94,8 +101,9 @@ __device__ inline double hash_uniform(unsigned long long x) {
 
 struct EigBufs {
   double* A;      // [nH][N][N] working matrix; later Z (eigenvectors of T)
-  double* Q;      // [nH][N][N] accumulated reflectors
-  double* P;      // [nH][N][N] psi^2
+  double* V;      // [nH][N][N] reflector j in row j (v_j, zero up to j)
+  double* taus;   // [nH][N] tau_j
+  double* Tb;     // [nH][nwy][kWy][kWy] compact WY factors
   double* lu;     // [nH][4][N][N] u0^-1, u1, u2, m of T_blk - lambda_t,
                   //  element (local row j, eigenvalue t) at j * N + t
   unsigned char* piv;   // [nH][N][N] row swap of elimination step j
@@ -110,7 +118,9 @@ struct EigBufs {
 
 size_t eig_workspace_bytes(int N, int nH) {
   const size_t n2 = (size_t)nH * N * N, n1 = (size_t)nH * N;
-  return 3 * al256(sizeof(double) * n2) + al256(sizeof(double) * 4 * n2) +
+  const size_t nwy = (size_t)nH * ((N + kWy - 1) / kWy) * kWy * kWy;
+  return 2 * al256(sizeof(double) * n2) + al256(sizeof(double) * n1) +
+         al256(sizeof(double) * nwy) + al256(sizeof(double) * 4 * n2) +
          al256(n2) + al256(sizeof(double) * 6 * n1) +
          al256(sizeof(double) * 2 * nH) + 4 * al256(sizeof(double) * n1) +
          al256(sizeof(int) * 2 * n1);
@@ -122,8 +132,10 @@ static EigBufs carve_eig(void* ws, int N, int nH) {
   EigBufs E;
   auto take = [&](size_t bytes) { char* r = c; c += al256(bytes); return r; };
   E.A = (double*)take(sizeof(double) * n2);
-  E.Q = (double*)take(sizeof(double) * n2);
-  E.P = (double*)take(sizeof(double) * n2);
+  E.V = (double*)take(sizeof(double) * n2);
+  E.taus = (double*)take(sizeof(double) * n1);
+  E.Tb = (double*)take(sizeof(double) * (size_t)nH * ((N + kWy - 1) / kWy) *
+                       kWy * kWy);
   E.lu = (double*)take(sizeof(double) * 4 * n2);
   E.piv = (unsigned char*)take(n2);
   E.vec = (double*)take(sizeof(double) * 6 * n1);
@@ -136,7 +148,7 @@ static EigBufs carve_eig(void* ws, int N, int nH) {
   return E;
 }
 
-// grid (N, nH): row i of H_hv (hopping of problem hv / 2) and of Q = I
+// grid (N, nH): row i of H_hv (hopping of problem hv / 2)
 __global__ void __launch_bounds__(256)
 eig_init_kernel(const ProbDesc* __restrict__ probs, const double* __restrict__ hbuf,
                 int N, int L, EigBufs E) {
@@ -144,22 +156,19 @@ eig_init_kernel(const ProbDesc* __restrict__ probs, const double* __restrict__ h
   const double t = probs[hv >> 1].t;
   const double hi = hbuf[(size_t)hv * N + i];
   double* A = E.A + ((size_t)hv * N + i) * N;
-  double* Q = E.Q + ((size_t)hv * N + i) * N;
-  for (int j = threadIdx.x; j < N; j += 256) {
+  for (int j = threadIdx.x; j < N; j += 256)
     A[j] = -t * (double)kmult(i, j, L) + (i == j ? hi : 0.0);
-    Q[j] = (i == j) ? 1.0 : 0.0;
-  }
 }
 
 // Householder step j (0 <= j < N), grid (ceil(N / 4), nH), 256 threads.
 // The reflector of column j-1 (v, tau, p = tau A_{j-1} v: support [j, N))
 // is pending from the previous launch; w = p - (tau/2)(p.v) v and
-// A_j = A_{j-1} - v w^T - w v^T on [j, N)^2, Q <- Q (I - tau v v^T).
+// A_j = A_{j-1} - v w^T - w v^T on [j, N)^2.
 // Column j of A_j is formed from the previous launch's copy of column j of
 // A_{j-1}; its entries below the diagonal give the reflector of column j
 // (v_{j+1} = 1, tau = (beta - alpha)/beta, beta = -sign(alpha) |x|).
 // Rows and columns below j+1 of A are never read again, so a wave keeps
-// only A[r][j+1 ..] of its row r > j (and Q[r][j ..]) in registers: lane
+// only A[r][j+1 ..] of its row r > j in registers: lane
 // holds columns c0 + lane + 64 k, k < KM; every global load of the launch
 // is issued before the first reduction.
 template <int KM>
@@ -169,7 +178,6 @@ hh_step_kernel(int N, int j, EigBufs E) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r = blockIdx.x * kRowsPerWg + w;   // this wave's row
   double* A = E.A + (size_t)hv * N * N;
-  double* Q = E.Q + (size_t)hv * N * N;
   double* vb = E.vec + (size_t)hv * 6 * N;
   double* taub = E.tau + 2 * hv;
   extern __shared__ double sm[];
@@ -180,13 +188,11 @@ hh_step_kernel(int N, int j, EigBufs E) {
   const int cur = j & 1, prv = cur ^ 1;
   const bool pend = j > 0;
   const bool rowA = r < N && r > j;    // A row of this wave still in play
-  const bool rowQ = pend && r < N;
-  double ar[KM], qr[KM];
+  double ar[KM];
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
-    const int ca = j + 1 + lane + 64 * k, cq = j + lane + 64 * k;
+    const int ca = j + 1 + lane + 64 * k;
     ar[k] = (rowA && ca < N) ? A[(size_t)r * N + ca] : 0.0;
-    qr[k] = (rowQ && cq < N) ? Q[(size_t)r * N + cq] : 0.0;
   }
   double tp = 0.0;
   if (pend) {
@@ -218,20 +224,6 @@ hh_step_kernel(int N, int j, EigBufs E) {
       if (c < N) ar[k] -= vr * sw[c] + wr * sv[c];
     }
   }
-  if (rowQ) {
-    double qv = 0.0;
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-      const int c = j + lane + 64 * k;
-      if (c < N) qv += qr[k] * sv[c];
-    }
-    qv = wave_sum(qv) * tp;
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-      const int c = j + lane + 64 * k;
-      if (c < N) Q[(size_t)r * N + c] = qr[k] - qv * sv[c];
-    }
-  }
   __syncthreads();
   if (j == N - 1) {   // last diagonal entry; no reflector
     if (blockIdx.x == 0 && tid == 0) E.d[(size_t)hv * N + j] = sx[j];
@@ -259,10 +251,16 @@ hh_step_kernel(int N, int j, EigBufs E) {
     if (tid == 0) {
       E.d[(size_t)hv * N + j] = dj;
       E.e[(size_t)hv * N + j] = beta;
+      E.taus[(size_t)hv * N + j] = tau;
       taub[cur] = tau;
     }
     double* vn = vb + cur * N;
-    for (int q = j + 1 + tid; q < N; q += 256) vn[q] = sx[q];
+    double* vrow = E.V + ((size_t)hv * N + j) * N;
+    for (int q = tid; q < N; q += 256) {
+      const double vq = q > j ? sx[q] : 0.0;
+      vrow[q] = vq;
+      if (q > j) vn[q] = vq;
+    }
   }
   // p = tau A_j v, the copy of column j+1 of A_j, and the row for the next
   // launch (columns j+2 ..; column j+1 travels in the copy)
@@ -670,48 +668,132 @@ mgs_kernel(int N, EigBufs E) {
   }
 }
 
-// grid (ceil(N / 64), ceil(N / 64), nH), 256 threads: P = (Q Z)^2 by 64x64
-// tiles, 16-deep slices of the contraction through LDS, 4x4 per thread.
+// grid (ceil((N - 1) / kWy), nH), 256 threads: T of the block of reflectors
+// j0 .. j0 + nb - 1 (forward, column by column: T_ii = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] V[:, 0:i]^T v_i), from the Gram matrix of
+// the block's vectors (rows staged through LDS 64 at a time).
 __global__ void __launch_bounds__(256)
-psi_sq_kernel(int N, EigBufs E) {
-  const int hv = blockIdx.z;
-  const int i0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
-  const double* Qm = E.Q + (size_t)hv * N * N;
-  const double* Z = E.A + (size_t)hv * N * N;
-  double* P = E.P + (size_t)hv * N * N;
-  __shared__ double qs[16][65];   // qs[j][i]
-  __shared__ double zs[16][65];   // zs[j][k]
-  const int tid = threadIdx.x, ti = tid >> 4, tk = tid & 15;
-  double acc[4][4] = {};
-  for (int j0 = 0; j0 < N; j0 += 16) {
-    for (int u = tid; u < 16 * 64; u += 256) {
-      const int jj = u & 15, ii = u >> 4;   // Q[i0+ii][j0+jj]
-      const int gi = i0 + ii, gj = j0 + jj;
-      qs[jj][ii] = (gi < N && gj < N) ? Qm[(size_t)gi * N + gj] : 0.0;
-      const int kk = u & 63, jz = u >> 6;   // Z[j0+jz][k0+kk]
-      const int zj = j0 + jz, zk = k0 + kk;
-      zs[jz][kk] = (zj < N && zk < N) ? Z[(size_t)zj * N + zk] : 0.0;
+wy_t_kernel(int N, EigBufs E) {
+  const int blk = blockIdx.x, hv = blockIdx.y, tid = threadIdx.x;
+  const int nref = N - 1, j0 = blk * kWy, nb = min(kWy, nref - j0);
+  const double* V = E.V + (size_t)hv * N * N;
+  __shared__ double vs[kWy][65];
+  __shared__ double G[kWy][kWy + 1];
+  __shared__ double T[kWy][kWy + 1];
+  // pairs (m, i): thread owns m = tid >> 3, i = (tid & 7) + 8 u, u < 4
+  const int m = tid >> 3;
+  double g[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = j0 + 1; r0 < N; r0 += 64) {
+    for (int u = tid; u < kWy * 64; u += 256) {
+      const int ii = u >> 6, rr = u & 63, r = r0 + rr;
+      vs[ii][rr] = (ii < nb && r < N) ? V[(size_t)(j0 + ii) * N + r] : 0.0;
     }
     __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < 64; ++rr) {
+      const double a = vs[m][rr];
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      double a[4], b[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) { a[x] = qs[jj][ti + 16 * x]; b[x] = zs[jj][tk + 16 * x]; }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+      for (int u = 0; u < 4; ++u) g[u] = fma(a, vs[(tid & 7) + 8 * u][rr], g[u]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int gi = i0 + ti + 16 * x, gk = k0 + tk + 16 * y;
-      if (gi < N && gk < N) P[(size_t)gi * N + gk] = acc[x][y] * acc[x][y];
+  for (int u = 0; u < 4; ++u) G[m][(tid & 7) + 8 * u] = g[u];
+  __syncthreads();
+  if (tid < 64) {
+    const int k = tid;   // row of T this lane builds
+    for (int i = 0; i < kWy; ++i) {
+      const double ti = i < nb ? E.taus[(size_t)hv * N + j0 + i] : 0.0;
+      double acc = 0.0;
+      if (k < i)
+        for (int mm = k; mm < i; ++mm) acc += T[k][mm] * G[mm][i];
+      if (k < kWy) T[k][i] = k < i ? -ti * acc : (k == i ? ti : 0.0);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
+  }
+  __syncthreads();
+  double* To = E.Tb + (((size_t)hv * gridDim.x + blk) * kWy) * kWy;
+  for (int u = tid; u < kWy * kWy; u += 256) To[u] = T[u / kWy][u % kWy];
+}
+
+// grid (ceil(N / kWyCols), nH), 256 threads: Z[:, k0 .. k0+16) <- Q Z by the
+// blocks from the last to the first, Z <- Z - V (T (V^T Z)) on the rows
+// below j0 of each block.  Thread: W entries (i = tid >> 3, columns
+// 2 (tid & 7) + {0, 1}); Z entries (rows rr = tid >> 4 + 16 u, column
+// tid & 15) of each 64-row chunk.
+__global__ void __launch_bounds__(256)
+wy_apply_kernel(int N, EigBufs E) {
+  const int hv = blockIdx.y, tid = threadIdx.x;
+  const int k0 = blockIdx.x * kWyCols;
+  const int nref = N - 1, nwy = (nref + kWy - 1) / kWy;
+  const double* V = E.V + (size_t)hv * N * N;
+  double* Z = E.A + (size_t)hv * N * N;
+  __shared__ double vs[kWy][65];
+  __shared__ double zs[64][kWyCols + 1];
+  __shared__ double ws[kWy][kWyCols + 1];
+  __shared__ double w2[kWy][kWyCols + 1];
+  __shared__ double ts[kWy][kWy + 1];
+  const int wi = tid >> 3, wk = 2 * (tid & 7);
+  const int zr = tid >> 4, zk = tid & 15;
+  for (int blk = nwy - 1; blk >= 0; --blk) {
+    const int j0 = blk * kWy, nb = min(kWy, nref - j0);
+    const double* Tg = E.Tb + (((size_t)hv * nwy + blk) * kWy) * kWy;
+    for (int u = tid; u < kWy * kWy; u += 256) ts[u / kWy][u % kWy] = Tg[u];
+    // W = V^T Z (this slice)
+    double a0 = 0.0, a1 = 0.0;
+    for (int r0 = j0 + 1; r0 < N; r0 += 64) {
+      for (int u = tid; u < kWy * 64; u += 256) {
+        const int ii = u >> 6, rr = u & 63, r = r0 + rr;
+        vs[ii][rr] = (ii < nb && r < N) ? V[(size_t)(j0 + ii) * N + r] : 0.0;
+      }
+      for (int u = tid; u < 64 * kWyCols; u += 256) {
+        const int rr = u >> 4, kk = u & 15, r = r0 + rr, c = k0 + kk;
+        zs[rr][kk] = (r < N && c < N) ? Z[(size_t)r * N + c] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int rr = 0; rr < 64; ++rr) {
+        const double v = vs[wi][rr];
+        a0 = fma(v, zs[rr][wk], a0);
+        a1 = fma(v, zs[rr][wk + 1], a1);
+      }
+      __syncthreads();
+    }
+    ws[wi][wk] = a0; ws[wi][wk + 1] = a1;
+    __syncthreads();
+    // W2 = T W (T upper triangular)
+    {
+      double b0 = 0.0, b1 = 0.0;
+      for (int mm = wi; mm < kWy; ++mm) {
+        const double t = ts[wi][mm];
+        b0 = fma(t, ws[mm][wk], b0);
+        b1 = fma(t, ws[mm][wk + 1], b1);
+      }
+      w2[wi][wk] = b0; w2[wi][wk + 1] = b1;
+    }
+    __syncthreads();
+    // Z -= V W2 on rows [j0 + 1, N)
+    for (int r0 = j0 + 1; r0 < N; r0 += 64) {
+      for (int u = tid; u < kWy * 64; u += 256) {
+        const int ii = u >> 6, rr = u & 63, r = r0 + rr;
+        vs[ii][rr] = (ii < nb && r < N) ? V[(size_t)(j0 + ii) * N + r] : 0.0;
+      }
+      __syncthreads();
+      const int c = k0 + zk;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = zr + 16 * u, r = r0 + rr;
+        if (r < N && c < N) {
+          double acc = 0.0;
+#pragma unroll 8
+          for (int ii = 0; ii < kWy; ++ii) acc = fma(vs[ii][rr], w2[ii][zk], acc);
+          Z[(size_t)r * N + c] -= acc;
+        }
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // grid (ceil(N / 64), ceil(B / 16)), 256 threads: rows [i0, i0+64) of the
@@ -746,14 +828,15 @@ expand_kernel(const MatDesc* __restrict__ descs, int B, int N, EigBufs E,
     unsigned mine = 0;
     for (int b = 0; b < 16; ++b)
       if (!(done >> b & 1) && hvs[b] == hv) mine |= 1u << b;
-    const double* P = E.P + (size_t)hv * N * N;
+    const double* Z = E.A + (size_t)hv * N * N;   // psi, squared on load
     const double* lam = E.lam + (size_t)hv * N;
     double ar[4] = {}, ai[4] = {};
     for (int k0 = 0; k0 < N; k0 += 16) {
       for (int u = tid; u < 16 * 64; u += 256) {
         const int kk = u & 15, ii = u >> 4;
         const int gi = i0 + ii, gk = k0 + kk;
-        ps[kk][ii] = (gi < N && gk < N) ? P[(size_t)gi * N + gk] : 0.0;
+        const double z = (gi < N && gk < N) ? Z[(size_t)gi * N + gk] : 0.0;
+        ps[kk][ii] = z * z;
       }
       {
         const int b = tid >> 4, kk = tid & 15, gk = k0 + kk;
@@ -840,7 +923,9 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
   }
   hipLaunchKernelGGL(mgs_kernel, dim3((N + 3) / 4, nH), dim3(256), 0, st, N,
                      E);
-  hipLaunchKernelGGL(psi_sq_kernel, dim3((N + 63) / 64, (N + 63) / 64, nH),
+  const int nwy = (N - 1 + kWy - 1) / kWy;
+  hipLaunchKernelGGL(wy_t_kernel, dim3(nwy, nH), dim3(256), 0, st, N, E);
+  hipLaunchKernelGGL(wy_apply_kernel, dim3((N + kWyCols - 1) / kWyCols, nH),
                      dim3(256), 0, st, N, E);
   mark_end(K_SPECTRUM, st);
   mark_begin(K_EXPAND, st);
