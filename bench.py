@@ -29,6 +29,7 @@ Prints one JSON line.  Besides the contract fields it carries
                 mixed requests through the request server, next to the
                 one-at-a-time FIFO baseline on the same GPU;
   serving_tail  the same stream with the Matsubara tail by moments;
+  serving_spectral the same stream on the spectral route;
   spectral      the spectral route (factor eigh: one eigendecomposition of
                 H per spin, every frequency from the spectrum) on the
                 workload with its per-class times, on the 48x48 ionic
@@ -304,7 +305,7 @@ def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0,
     del ctx
     return {"workload": (f"{n_req} requests, L in {sorted(set(Ls))}, "
                          f"n_max={n_max}, {steps} ADAM steps each, FP64 "
-                         f"({'pivoted LU' if factor == 'lu' else 'L D L^T'}"
+                         f"({ {'lu': 'pivoted LU', 'ldlt': 'L D L^T', 'eigh': 'spectral'}[factor] }"
                          f"{', Matsubara tail by moments' if tail else ''}), "
                          f"U~U[2,8], Delta~U[0,2], T~U[0.05,0.6]"),
             "arrivals": f"Poisson, {rate:.3f}/s = {load} x FIFO capacity",
@@ -490,6 +491,13 @@ def main():
                                           args.serving_batch,
                                           factor=args.serving_factor,
                                           tail=True)
+        if not args.no_spectral:
+            # the same stream on the spectral route
+            out["serving_spectral"] = serving(sca, args.serving_requests,
+                                              args.serving_steps,
+                                              args.serving_nmax, Ls,
+                                              args.serving_batch,
+                                              factor="eigh")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
