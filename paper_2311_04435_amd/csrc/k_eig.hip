@@ -796,6 +796,80 @@ wy_apply_kernel(int N, EigBufs E) {
   }
 }
 
+// N <= kWyLdsMax: the same back-transformation with the workgroup's slice of
+// Z (4 columns) resident in LDS for the whole kernel and each block of V
+// loaded into LDS once (one round of global loads per block instead of one
+// per 64-row chunk and phase).  Thread roles: W entries (i, k) = ((t >> 1)
+// >> 2, (t >> 1) & 3) over rows of parity t & 1; Z entries (rows
+// j0 + 1 + (t >> 2) + 64 m, column t & 3).
+constexpr int kWyLdsMax = 512;
+constexpr int kWyLdsCols = 4;
+__host__ __device__ constexpr size_t wy_lds_bytes(int N) {
+  return sizeof(double) * ((size_t)(kWy + kWyLdsCols) * N +
+                           kWy * (kWy + 1) + 2 * kWy * kWyLdsCols);
+}
+__global__ void __launch_bounds__(256)
+wy_apply_lds_kernel(int N, EigBufs E) {
+  const int hv = blockIdx.y, tid = threadIdx.x;
+  const int k0 = blockIdx.x * kWyLdsCols;
+  const int nref = N - 1, nwy = (nref + kWy - 1) / kWy;
+  const double* V = E.V + (size_t)hv * N * N;
+  double* Z = E.A + (size_t)hv * N * N;
+  extern __shared__ double sm[];
+  double* vsb = sm;                                  // [kWy][N]
+  double* zs = vsb + (size_t)kWy * N;                // [N][4]
+  double* ts = zs + (size_t)kWyLdsCols * N;          // [kWy][kWy + 1]
+  double* ws = ts + kWy * (kWy + 1);                 // [kWy][4]
+  double* w2 = ws + kWy * kWyLdsCols;                // [kWy][4]
+  for (int u = tid; u < N * kWyLdsCols; u += 256) {
+    const int r = u >> 2, kk = u & 3, c = k0 + kk;
+    zs[u] = c < N ? Z[(size_t)r * N + c] : 0.0;
+  }
+  const int pi = (tid >> 1) >> 2, pk = (tid >> 1) & 3, ph = tid & 1;
+  const int zk = tid & 3, zr = tid >> 2;
+  for (int blk = nwy - 1; blk >= 0; --blk) {
+    const int j0 = blk * kWy, nb = min(kWy, nref - j0), r0 = j0 + 1;
+    const int nr = N - r0;
+    const double* Tg = E.Tb + (((size_t)hv * nwy + blk) * kWy) * kWy;
+    __syncthreads();   // previous block done with vsb, ws, w2
+    for (int u = tid; u < kWy * kWy; u += 256) ts[(u / kWy) * (kWy + 1) + u % kWy] = Tg[u];
+    for (int u = tid; u < kWy * nr; u += 256) {
+      const int ii = u / nr, rr = u - ii * nr;
+      vsb[ii * N + rr] = ii < nb ? V[(size_t)(j0 + ii) * N + r0 + rr] : 0.0;
+    }
+    __syncthreads();
+    // W = V^T Z
+    double a = 0.0;
+    for (int rr = ph; rr < nr; rr += 2)
+      a = fma(vsb[pi * N + rr], zs[(r0 + rr) * kWyLdsCols + pk], a);
+    a += __shfl_xor(a, 1);
+    if (ph == 0) ws[pi * kWyLdsCols + pk] = a;
+    __syncthreads();
+    // W2 = T W
+    if (tid < kWy * kWyLdsCols) {
+      const int i = tid >> 2, k = tid & 3;
+      double b = 0.0;
+      for (int mm = i; mm < kWy; ++mm)
+        b = fma(ts[i * (kWy + 1) + mm], ws[mm * kWyLdsCols + k], b);
+      w2[i * kWyLdsCols + k] = b;
+    }
+    __syncthreads();
+    // Z -= V W2
+    for (int rr = zr; rr < nr; rr += 64) {
+      double acc = 0.0;
+#pragma unroll 8
+      for (int ii = 0; ii < kWy; ++ii)
+        acc = fma(vsb[ii * N + rr], w2[ii * kWyLdsCols + zk], acc);
+      zs[(r0 + rr) * kWyLdsCols + zk] -= acc;
+    }
+  }
+  __syncthreads();
+  for (int u = tid; u < N * kWyLdsCols; u += 256) {
+    const int r = u >> 2, kk = u & 3, c = k0 + kk;
+    if (c < N) Z[(size_t)r * N + c] = zs[u];
+  }
+}
+
 // grid (ceil(N / 64), ceil(B / 16)), 256 threads: rows [i0, i0+64) of the
 // matrices [b0, b0+16).  Matrices of one tile that belong to different h
 // vectors are done in turns (one per distinct h vector).  Thread: row
@@ -925,8 +999,17 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
                      E);
   const int nwy = (N - 1 + kWy - 1) / kWy;
   hipLaunchKernelGGL(wy_t_kernel, dim3(nwy, nH), dim3(256), 0, st, N, E);
-  hipLaunchKernelGGL(wy_apply_kernel, dim3((N + kWyCols - 1) / kWyCols, nH),
-                     dim3(256), 0, st, N, E);
+  if (N <= kWyLdsMax) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(wy_apply_lds_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)wy_lds_bytes(N));
+    hipLaunchKernelGGL(wy_apply_lds_kernel,
+                       dim3((N + kWyLdsCols - 1) / kWyLdsCols, nH), dim3(256),
+                       wy_lds_bytes(N), st, N, E);
+  } else {
+    hipLaunchKernelGGL(wy_apply_kernel, dim3((N + kWyCols - 1) / kWyCols, nH),
+                       dim3(256), 0, st, N, E);
+  }
   mark_end(K_SPECTRUM, st);
   mark_begin(K_EXPAND, st);
   if (dg)
