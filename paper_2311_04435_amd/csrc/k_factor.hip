@@ -1164,11 +1164,11 @@ BlockedPlan blocked_plan(int N, bool fp32) {
     else if (n32 <= 512) { p.cfg = 1; p.NB = 32; p.Np = n32; }
     else if (n16 <= 1024) { p.cfg = 2; p.NB = 16; p.Np = n16; }
   } else {
-    const int n64 = (N + 63) / 64 * 64;
-    if (n64 <= 256) { p.cfg = 0; p.NB = 32; p.Np = n64; }
-    else if (n64 <= 512) { p.cfg = 1; p.NB = 32; p.Np = n64; }
-    else if (n64 <= 1024) { p.cfg = 2; p.NB = 32; p.Np = n64; }
-    else if (n64 <= 2304) { p.cfg = 3; p.NB = 16; p.Np = n64; }
+    const int n32 = (N + 31) / 32 * 32;
+    if (n32 <= 256) { p.cfg = 0; p.NB = 32; p.Np = n32; }
+    else if (n32 <= 512) { p.cfg = 1; p.NB = 32; p.Np = n32; }
+    else if (n32 <= 1024) { p.cfg = 2; p.NB = 32; p.Np = n32; }
+    else if (n32 <= 2304) { p.cfg = 3; p.NB = 16; p.Np = n32; }
   }
   if (p.cfg < 0) { p.NB = 0; p.Np = 0; }
   return p;
@@ -1219,7 +1219,7 @@ hipError_t blocked_lu_f32(const BlockedPlan& p, const MatDesc* descs,
                           hipStream_t st) {
   switch (p.cfg) {
     case 0: return run_lu<float, 4, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
-    case 1: return run_lu<float, 8, 4, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 1: return run_lu<float, 8, 4, 2, true>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     case 2: return run_lu<float, 8, 8, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     case 3: return run_lu<float, 8, 18, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     default: return hipErrorInvalidValue;

@@ -42,7 +42,8 @@ constexpr int GK = 16;   // k chunk
 // X[i][c] = sum_{k >= max(i, c)} W[i][k] V[k][c], V[c][c] = 1.
 // W[i][k] is stored at F[perm[i]][k] (k >= i), V[k][c] at F[perm[k]][c]
 // (k > c).  256 threads: 4 waves, each a 32 x 32 quarter of the 64 x 64 tile
-// (2 x 2 MFMA tiles, real and imaginary accumulators).
+// (2 x 2 MFMA tiles, real and imaginary accumulators).  Np is a multiple of
+// 16; the tiles past Np are masked.
 __global__ void __launch_bounds__(256)
 wv_gemm_kernel(int Np, const float* __restrict__ F, const int* __restrict__ perm_g,
                float* __restrict__ X) {
@@ -58,7 +59,7 @@ wv_gemm_kernel(int Np, const float* __restrict__ F, const int* __restrict__ perm
   const float* Fr = F + (size_t)b * 2 * plane;
   const float* Fi = Fr + plane;
   const int* perm = perm_g + (size_t)b * Np;
-  if (tid < GT) prow[tid] = perm[i0 + tid];
+  if (tid < GT) prow[tid] = i0 + tid < Np ? perm[i0 + tid] : 0;
   f4 ar[2][2], ai[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -76,7 +77,7 @@ wv_gemm_kernel(int Np, const float* __restrict__ F, const int* __restrict__ perm
       const int r = e / GK, k = e % GK;
       const int gi = i0 + r, gk = k0 + k;
       float xr = 0.f, xi = 0.f;
-      if (gk >= gi) {
+      if (gk >= gi && gi < Np) {
         const size_t o = (size_t)prow[r] * Np + gk;
         xr = Fr[o];
         xi = Fi[o];
@@ -90,7 +91,9 @@ wv_gemm_kernel(int Np, const float* __restrict__ F, const int* __restrict__ perm
       const int k = e / GT, c = e % GT;
       const int gk = k0 + k, gc = c0 + c;
       float vr = 0.f, vi = 0.f;
-      if (gk > gc) {
+      if (gc >= Np) {
+        // masked column
+      } else if (gk > gc) {
         const size_t o = (size_t)pk[k] * Np + gc;
         vr = Fr[o];
         vi = Fi[o];
@@ -127,9 +130,12 @@ wv_gemm_kernel(int Np, const float* __restrict__ F, const int* __restrict__ perm
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const size_t o = (size_t)(i0 + wr + 16 * a + 4 * g + j) * Np + c0 + wc + 16 * c + q;
-        Xr[o] = ar[a][c][j];
-        Xi[o] = ai[a][c][j];
+        const int gi = i0 + wr + 16 * a + 4 * g + j, gc = c0 + wc + 16 * c + q;
+        if (gi < Np && gc < Np) {
+          const size_t o = (size_t)gi * Np + gc;
+          Xr[o] = ar[a][c][j];
+          Xi[o] = ai[a][c][j];
+        }
       }
 }
 
@@ -137,7 +143,8 @@ wv_gemm_kernel(int Np, const float* __restrict__ F, const int* __restrict__ perm
 
 namespace {
 constexpr int RQ = 32;   // pivot positions per workgroup
-constexpr int RS = 32;   // s (or k) chunk
+constexpr int RS = 32;   // s chunk (Newton step)
+constexpr int RK = 16;   // k chunk (log-det: rows of W staged in LDS)
 }  // namespace
 
 __global__ void __launch_bounds__(256)
@@ -159,9 +166,17 @@ refine_kernel(int N, int Np, int L, const MatDesc* __restrict__ descs,
 
   __shared__ int iq[RQ];                       // i = perm[q]
   __shared__ int nbr[RQ][5];                   // {i} and its 4 neighbours
-  __shared__ double zr_s[RQ][RS + 1], zi_s[RQ][RS + 1];     // X[i][s-chunk]
-  __shared__ double ar_s[RS][RQ + 1], ai_s[RS][RQ + 1];     // (A Z)[perm s][i]
-  __shared__ float vr_s[RS][RQ + 1], vi_s[RS][RQ + 1];      // V[k][q]
+  // Newton step: X[i][s-chunk] and (A Z)[perm s][i]; the log-det phase
+  // reuses the same space for its chunk of the 5 RQ rows of W
+  __shared__ double nw_s[2 * RQ * (RS + 1) + 2 * RS * (RQ + 1)];
+  double (*zr_s)[RS + 1] = reinterpret_cast<double (*)[RS + 1]>(nw_s);
+  double (*zi_s)[RS + 1] = zr_s + RQ;
+  double (*ar_s)[RQ + 1] = reinterpret_cast<double (*)[RQ + 1]>(nw_s + 2 * RQ * (RS + 1));
+  double (*ai_s)[RQ + 1] = ar_s + RS;
+  float (*wr_s)[RK + 1] = reinterpret_cast<float (*)[RK + 1]>(nw_s);
+  float (*wi_s)[RK + 1] = wr_s + 5 * RQ;
+  __shared__ float vr_s[RK][RQ + 1], vi_s[RK][RQ + 1];      // V[k][q]
+  __shared__ int wrow_s[5 * RQ], jrow_s[5 * RQ];
   __shared__ double part_r[8][RQ], part_i[8][RQ];
   __shared__ double tr_part[256], ld_part[RQ];
 
@@ -208,8 +223,8 @@ refine_kernel(int N, int Np, int L, const MatDesc* __restrict__ descs,
       if (s < Np && q < Np) {
         const int r = perm[s];
         if (r < N) {
-          const size_t o = (size_t)r * Np + q;
           const double cr = dsc.zr - h[r], ci = dsc.zi;
+          const size_t o = (size_t)r * Np + q;
           const double xr = Xr[o], xi = Xi[o];
           vr = cr * xr - ci * xi;
           vi = cr * xi + ci * xr;
@@ -252,16 +267,32 @@ refine_kernel(int N, int Np, int L, const MatDesc* __restrict__ descs,
   }
 
   // ---- log-det: tr(A Y) over this block's columns, -sum ln|w_qq| ---------
-  // thread (a, k5) with a = tid / 5 < RQ handles Y_{nbr[a][k5], i_a}
+  // thread (a, k5) with a = tid / 5 < RQ handles Y_{nbr[a][k5], i_a}; the
+  // rows of W it needs are staged in LDS a chunk of RK columns at a time
   const int a5 = tid / 5, k5 = tid % 5;
   const bool act = (tid < 5 * RQ) && (a5 < RQ) && nbr[a5 < RQ ? a5 : 0][k5] >= 0;
   const int jrow = act ? nbr[a5][k5] : 0;
   double yr = 0.0, yi = 0.0;
   // W[j][k] lives at F[perm[j]][k] for k >= j
-  const int wrow = act ? perm[jrow] : 0;
-  for (int k0 = 0; k0 < Np; k0 += RS) {
+  if (tid < 5 * RQ) {
+    wrow_s[tid] = act ? perm[jrow] : -1;
+    jrow_s[tid] = jrow;
+  }
+  for (int k0 = 0; k0 < Np; k0 += RK) {
     __syncthreads();
-    for (int e = tid; e < RS * RQ; e += 256) {
+    for (int e = tid; e < 5 * RQ * RK; e += 256) {
+      const int p = e / RK, kl = e % RK, k = k0 + kl;
+      const int wr = wrow_s[p];
+      float xr = 0.f, xi = 0.f;
+      if (wr >= 0 && k < Np && k >= jrow_s[p]) {
+        const size_t o = (size_t)wr * Np + k;
+        xr = Fr[o];
+        xi = Fi[o];
+      }
+      wr_s[p][kl] = xr;
+      wi_s[p][kl] = xi;
+    }
+    for (int e = tid; e < RK * RQ; e += 256) {
       const int kl = e / RQ, a = e % RQ;
       const int k = k0 + kl, q = q0 + a;
       float vr = 0.f, vi = 0.f;
@@ -279,11 +310,9 @@ refine_kernel(int N, int Np, int L, const MatDesc* __restrict__ descs,
     }
     __syncthreads();
     if (act) {
-      for (int kl = 0; kl < RS; ++kl) {
-        const int k = k0 + kl;
-        if (k < jrow || k >= Np) continue;
-        const size_t o = (size_t)wrow * Np + k;
-        const double wr_ = Fr[o], wi_ = Fi[o];
+#pragma unroll
+      for (int kl = 0; kl < RK; ++kl) {
+        const double wr_ = wr_s[tid][kl], wi_ = wi_s[tid][kl];
         const double vr = vr_s[kl][a5], vi = vi_s[kl][a5];
         yr += wr_ * vr - wi_ * vi;
         yi += wr_ * vi + wi_ * vr;
@@ -339,9 +368,10 @@ int refine_blocks(int Np) { return (Np + RQ - 1) / RQ; }
 
 hipError_t launch_wv_gemm(int B, int Np, const float* F, const int* perm,
                           float* X, hipStream_t st) {
-  if (Np % GT) return hipErrorInvalidValue;
+  if (Np % GK) return hipErrorInvalidValue;
+  const int nt = (Np + GT - 1) / GT;
   mark_begin(K_WVGEMM, st);
-  hipLaunchKernelGGL(wv_gemm_kernel, dim3(Np / GT, Np / GT, B), dim3(256), 0,
+  hipLaunchKernelGGL(wv_gemm_kernel, dim3(nt, nt, B), dim3(256), 0,
                      st, Np, F, perm, X);
   mark_end(K_WVGEMM, st);
   return hipGetLastError();
