@@ -46,7 +46,7 @@ namespace sca {
 
 namespace {
 
-constexpr int kRowsPerWg = 4;     // hh_step: one wave per row
+constexpr int kRowsPerWg = 4;     // hh_step (N <= 512): one wave per row
 constexpr int kWy = 32;           // reflectors per compact WY block
 constexpr int kWyCols = 16;       // columns of Z per back-transform workgroup
 constexpr int kBisRounds = 10;    // 65^-10 of the Gershgorin width
@@ -78,14 +78,19 @@ __device__ inline int wave_mini(int v) {
   return v;
 }
 
-// sum over the 256 threads of a workgroup (every thread gets the result)
+// sum over the W waves of a workgroup (every thread gets the result; the
+// waves' partial sums are added in wave order)
+template <int W = 4>
 __device__ inline double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
+  double s = red[0];
+#pragma unroll
+  for (int k = 1; k < W; ++k) s += red[k];
+  return s;
 }
 
 // uniform in (-1, 1) from a 64-bit counter (SplitMix64 finaliser)
@@ -171,12 +176,13 @@ eig_init_kernel(const ProbDesc* __restrict__ probs, const double* __restrict__ h
 // only A[r][j+1 ..] of its row r > j in registers: lane
 // holds columns c0 + lane + 64 k, k < KM; every global load of the launch
 // is issued before the first reduction.
-template <int KM>
-__global__ void __launch_bounds__(256)
+template <int KM, int WV>
+__global__ void __launch_bounds__(WV * 64)
 hh_step_kernel(int N, int j, EigBufs E) {
+  constexpr int NT = WV * 64;
   const int hv = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r = blockIdx.x * kRowsPerWg + w;   // this wave's row
+  const int r = blockIdx.x * WV + w;   // this wave's row
   double* A = E.A + (size_t)hv * N * N;
   double* vb = E.vec + (size_t)hv * 6 * N;
   double* taub = E.tau + 2 * hv;
@@ -184,7 +190,7 @@ hh_step_kernel(int N, int j, EigBufs E) {
   double* sv = sm;            // pending v
   double* sw = sm + N;        // pending w
   double* sx = sm + 2 * N;    // column j of A_j, then the new v
-  __shared__ double red[4];
+  __shared__ double red[WV];
   const int cur = j & 1, prv = cur ^ 1;
   const bool pend = j > 0;
   const bool rowA = r < N && r > j;    // A row of this wave still in play
@@ -201,19 +207,19 @@ hh_step_kernel(int N, int j, EigBufs E) {
     const double* pp = vb + (2 + prv) * N;
     const double* cp = vb + (4 + prv) * N;
     double s = 0.0;
-    for (int c = j + tid; c < N; c += 256) {
+    for (int c = j + tid; c < N; c += NT) {
       const double a = vp[c], b = pp[c];
       sv[c] = a; sw[c] = b; sx[c] = cp[c]; s += a * b;
     }
-    s = block_sum(s, red);
+    s = block_sum<WV>(s, red);
     const double K = 0.5 * tp * s;
-    for (int c = j + tid; c < N; c += 256) sw[c] -= K * sv[c];
+    for (int c = j + tid; c < N; c += NT) sw[c] -= K * sv[c];
     __syncthreads();
     // column j of A_j, rows [j, N)
     const double wj = sw[j], vj = sv[j];
-    for (int q = j + tid; q < N; q += 256) sx[q] -= sv[q] * wj + sw[q] * vj;
+    for (int q = j + tid; q < N; q += NT) sx[q] -= sv[q] * wj + sw[q] * vj;
   } else {
-    for (int q = tid; q < N; q += 256) sx[q] = A[(size_t)q * N];
+    for (int q = tid; q < N; q += NT) sx[q] = A[(size_t)q * N];
   }
   // pending update of this wave's rows (registers)
   if (rowA && pend) {
@@ -232,8 +238,8 @@ hh_step_kernel(int N, int j, EigBufs E) {
   // reflector of column j from x = sx[j+1 .. N)
   const double alpha = sx[j + 1];
   double s = 0.0;
-  for (int q = j + 2 + tid; q < N; q += 256) s += sx[q] * sx[q];
-  s = block_sum(s, red);
+  for (int q = j + 2 + tid; q < N; q += NT) s += sx[q] * sx[q];
+  s = block_sum<WV>(s, red);
   double tau, beta, scale;
   if (s == 0.0) {
     tau = 0.0; beta = alpha; scale = 0.0;
@@ -245,7 +251,7 @@ hh_step_kernel(int N, int j, EigBufs E) {
   }
   const double dj = sx[j];
   __syncthreads();   // every thread has read alpha and dj
-  for (int q = j + 1 + tid; q < N; q += 256) sx[q] = (q == j + 1) ? 1.0 : sx[q] * scale;
+  for (int q = j + 1 + tid; q < N; q += NT) sx[q] = (q == j + 1) ? 1.0 : sx[q] * scale;
   __syncthreads();
   if (blockIdx.x == 0) {
     if (tid == 0) {
@@ -256,7 +262,7 @@ hh_step_kernel(int N, int j, EigBufs E) {
     }
     double* vn = vb + cur * N;
     double* vrow = E.V + ((size_t)hv * N + j) * N;
-    for (int q = tid; q < N; q += 256) {
+    for (int q = tid; q < N; q += NT) {
       const double vq = q > j ? sx[q] : 0.0;
       vrow[q] = vq;
       if (q > j) vn[q] = vq;
@@ -975,11 +981,16 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
   mark_begin(K_TRIDIAG, st);
   hipLaunchKernelGGL(eig_init_kernel, dim3(N, nH), dim3(256), 0, st, probs,
                      hbuf, N, L, E);
-  const int nrow = (N + kRowsPerWg - 1) / kRowsPerWg;
-  auto kern = N <= 512 ? hh_step_kernel<8> : N <= 1024 ? hh_step_kernel<16>
-            : N <= 2560 ? hh_step_kernel<40> : hh_step_kernel<64>;
+  // rows (waves) per workgroup: 4 up to N = 512, 8 above (measured: 8 is
+  // 6% faster at N = 1024, 2% slower at 400; 2 and 16 slower at both)
+  const bool wide = N > 512;
+  const int wv = wide ? 8 : kRowsPerWg;
+  const int nrow = (N + wv - 1) / wv;
+  auto kern = N <= 512 ? hh_step_kernel<8, kRowsPerWg>
+            : N <= 1024 ? hh_step_kernel<16, 8>
+            : N <= 2560 ? hh_step_kernel<40, 8> : hh_step_kernel<64, 8>;
   for (int j = 0; j < N; ++j)
-    hipLaunchKernelGGL(kern, dim3(nrow, nH), dim3(256),
+    hipLaunchKernelGGL(kern, dim3(nrow, nH), dim3(wv * 64),
                        sizeof(double) * 3 * N, st, N, j, E);
   mark_end(K_TRIDIAG, st);
   mark_begin(K_SPECTRUM, st);
