@@ -24,7 +24,10 @@
 //                      eigenvalue: 64 Sturm counts per round (65-section),
 //                      ten rounds.
 //   invit_kernel       one lane per eigenvalue: pivoted LU of T_blk - lambda,
-//                      three solves from a counter-hashed start vector.
+//                      three solves from a counter-hashed start vector
+//                      (invit_lds_kernel for N <= 512: one wave per
+//                      eigenvalue with the block of T and the factors in
+//                      LDS, the same arithmetic).
 //   mgs_kernel         eigenvalues of one block closer than 1e-4 |T_blk| form
 //                      a cluster; its vectors are orthonormalised (modified
 //                      Gram-Schmidt, two passes) in index order.
@@ -32,7 +35,9 @@
 //                      H_j0 .. H_j0+31 = I - V T V^T (Schreiber & Van Loan)
 //   wy_apply_kernel    psi = Q Z in place: the blocks applied to Z from the
 //                      last to the first, each workgroup on its own slice
-//                      of 16 columns (no dependency between workgroups)
+//                      of 16 columns (no dependency between workgroups);
+//                      wy_apply_lds_kernel for N <= 512 keeps a 4-column
+//                      slice of Z and each block of V in LDS.
 //   expand_kernel      dg[b][i] = sum_k psi_k(i)^2 / (z_b - lambda_k)
 //   lad_kernel         lad[b] = sum_k ln|z_b - lambda_k|, growth[b] = 1
 #include <float.h>
