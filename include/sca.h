@@ -246,7 +246,10 @@ SCA_API sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
                                  const double* phi, void* factors,
                                  double* grad);
 
-/* Kernel timing (tracing).  sca_profile(ctx, 1) resets the counters and
+/* Kernel timing (tracing).  With SCA_ROCTX=1 in the environment (read once
+ * per process) the library also brackets every kernel class's launches
+ * with a roctx range named "sca:<class>" (rocprofv3 --marker-trace).
+ * sca_profile(ctx, 1) resets the counters and
  * brackets every later kernel launch of this context with HIP events on its
  * stream; sca_profile(ctx, 0) stops.  sca_profile_read fills HOST arrays of
  * SCA_PROFILE_SLOTS entries with the accumulated milliseconds and launch

@@ -1,6 +1,30 @@
 #include "sca_profile.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
+#include <cstdlib>
+#include <cstring>
+
 namespace sca {
+
+bool roctx_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("SCA_ROCTX");
+    return v && std::strcmp(v, "0") != 0 && v[0] != '\0';
+  }();
+  return on;
+}
+
+void roctx_push(int k) {
+  static const char* const names[K_COUNT] = {
+      "sca:small", "sca:lu", "sca:trtri", "sca:diagdot", "sca:reduce",
+      "sca:setup", "sca:refine", "sca:wvgemm", "sca:ldlt", "sca:trtri_sym",
+      "sca:symdiag", "sca:fallback", "sca:tail", "sca:tridiag",
+      "sca:spectrum", "sca:expand"};
+  roctxRangePushA(k >= 0 && k < K_COUNT ? names[k] : "sca:?");
+}
+
+void roctx_pop() { (void)roctxRangePop(); }
 
 Profiler*& current_profiler() {
   static thread_local Profiler* p = nullptr;

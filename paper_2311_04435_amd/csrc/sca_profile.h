@@ -47,13 +47,22 @@ struct Profiler {
 // Profiler of the current call on this thread (nullptr: not timing).
 Profiler*& current_profiler();
 
+// roctx ranges (SCA_ROCTX=1 in the environment, read once): every kernel
+// class's launches are bracketed on the host by a range named after the
+// class (rocprofv3 --marker-trace records them).
+bool roctx_enabled();
+void roctx_push(int k);
+void roctx_pop();
+
 inline void mark_begin(int k, hipStream_t st) {
+  if (roctx_enabled()) roctx_push(k);
   Profiler* p = current_profiler();
   if (p && p->on) p->begin(k, st);
 }
 inline void mark_end(int k, hipStream_t st) {
   Profiler* p = current_profiler();
   if (p && p->on) p->end(k, st);
+  if (roctx_enabled()) roctx_pop();
 }
 
 }  // namespace sca
