@@ -35,7 +35,8 @@
 //                      H_j0 .. H_j0+31 = I - V T V^T (Schreiber & Van Loan)
 //   wy_apply_kernel    psi = Q Z in place: the blocks applied to Z from the
 //                      last to the first, each workgroup on its own slice
-//                      of 16 columns (no dependency between workgroups);
+//                      of 16 columns (no dependency between workgroups),
+//                      V^T Z and V W2 on the f64 MFMA;
 //                      wy_apply_lds_kernel for N <= 512 keeps a 4-column
 //                      slice of Z and each block of V in LDS.
 //   expand_kernel      dg[b][i] = sum_k psi_k(i)^2 / (z_b - lambda_k)
@@ -730,29 +731,32 @@ wy_t_kernel(int N, EigBufs E) {
 
 // grid (ceil(N / kWyCols), nH), 256 threads: Z[:, k0 .. k0+16) <- Q Z by the
 // blocks from the last to the first, Z <- Z - V (T (V^T Z)) on the rows
-// below j0 of each block.  Thread: W entries (i = tid >> 3, columns
-// 2 (tid & 7) + {0, 1}); Z entries (rows rr = tid >> 4 + 16 u, column
-// tid & 15) of each 64-row chunk.
+// below j0 of each block, both products on the f64 MFMA (16x16x4; A[m][k]
+// from lane k*16+m, B[k][n] from lane k*16+n, accumulator element e of lane
+// g*16+n holds row g+4e).  Each 64-row chunk of V and Z is staged in LDS:
+// W = V^T Z takes the chunk's rows in steps of 4 split over the waves
+// (partial sums reduced through LDS); Z -= V W2 gives each wave one
+// 16-row tile.
 __global__ void __launch_bounds__(256)
 wy_apply_kernel(int N, EigBufs E) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
   const int hv = blockIdx.y, tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, q = lane & 15;
   const int k0 = blockIdx.x * kWyCols;
   const int nref = N - 1, nwy = (nref + kWy - 1) / kWy;
   const double* V = E.V + (size_t)hv * N * N;
   double* Z = E.A + (size_t)hv * N * N;
-  __shared__ double vs[kWy][65];
-  __shared__ double zs[64][kWyCols + 1];
-  __shared__ double ws[kWy][kWyCols + 1];
+  __shared__ double vs[kWy][65];                 // V[j0 + i][r0 + rr]
+  __shared__ double zs[64][kWyCols + 1];         // Z[r0 + rr][k0 + n]
+  __shared__ double wp[4][kWy][kWyCols + 1];     // per-wave partial W
   __shared__ double w2[kWy][kWyCols + 1];
   __shared__ double ts[kWy][kWy + 1];
-  const int wi = tid >> 3, wk = 2 * (tid & 7);
-  const int zr = tid >> 4, zk = tid & 15;
   for (int blk = nwy - 1; blk >= 0; --blk) {
     const int j0 = blk * kWy, nb = min(kWy, nref - j0);
     const double* Tg = E.Tb + (((size_t)hv * nwy + blk) * kWy) * kWy;
     for (int u = tid; u < kWy * kWy; u += 256) ts[u / kWy][u % kWy] = Tg[u];
-    // W = V^T Z (this slice)
-    double a0 = 0.0, a1 = 0.0;
+    // W = V^T Z: wave w takes row steps rr = 4 (w + 4 s), s < 4, of each chunk
+    v4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
     for (int r0 = j0 + 1; r0 < N; r0 += 64) {
       for (int u = tid; u < kWy * 64; u += 256) {
         const int ii = u >> 6, rr = u & 63, r = r0 + rr;
@@ -763,44 +767,51 @@ wy_apply_kernel(int N, EigBufs E) {
         zs[rr][kk] = (r < N && c < N) ? Z[(size_t)r * N + c] : 0.0;
       }
       __syncthreads();
-#pragma unroll 8
-      for (int rr = 0; rr < 64; ++rr) {
-        const double v = vs[wi][rr];
-        a0 = fma(v, zs[rr][wk], a0);
-        a1 = fma(v, zs[rr][wk + 1], a1);
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int rr = 4 * (w + 4 * st) + g;   // this lane's k (row)
+        const double b = zs[rr][q];
+        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(vs[q][rr], b, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vs[16 + q][rr], b, c1, 0, 0, 0);
       }
       __syncthreads();
     }
-    ws[wi][wk] = a0; ws[wi][wk + 1] = a1;
-    __syncthreads();
-    // W2 = T W (T upper triangular)
-    {
-      double b0 = 0.0, b1 = 0.0;
-      for (int mm = wi; mm < kWy; ++mm) {
-        const double t = ts[wi][mm];
-        b0 = fma(t, ws[mm][wk], b0);
-        b1 = fma(t, ws[mm][wk + 1], b1);
-      }
-      w2[wi][wk] = b0; w2[wi][wk + 1] = b1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      wp[w][g + 4 * e][q] = c0[e];
+      wp[w][16 + g + 4 * e][q] = c1[e];
     }
     __syncthreads();
-    // Z -= V W2 on rows [j0 + 1, N)
+    // W2 = T W (T upper triangular); W = sum of the waves' parts in order
+    for (int u = tid; u < kWy * kWyCols; u += 256) {
+      const int i = u >> 4, n = u & 15;
+      double b = 0.0;
+      for (int mm = i; mm < kWy; ++mm) {
+        const double wv = ((wp[0][mm][n] + wp[1][mm][n]) + wp[2][mm][n]) + wp[3][mm][n];
+        b = fma(ts[i][mm], wv, b);
+      }
+      w2[i][n] = b;
+    }
+    __syncthreads();
+    // Z -= V W2: wave w takes rows [r0 + 16 w, +16) of each chunk
     for (int r0 = j0 + 1; r0 < N; r0 += 64) {
       for (int u = tid; u < kWy * 64; u += 256) {
         const int ii = u >> 6, rr = u & 63, r = r0 + rr;
         vs[ii][rr] = (ii < nb && r < N) ? V[(size_t)(j0 + ii) * N + r] : 0.0;
       }
       __syncthreads();
-      const int c = k0 + zk;
+      v4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int rr = zr + 16 * u, r = r0 + rr;
-        if (r < N && c < N) {
-          double acc = 0.0;
-#pragma unroll 8
-          for (int ii = 0; ii < kWy; ++ii) acc = fma(vs[ii][rr], w2[ii][zk], acc);
-          Z[(size_t)r * N + c] -= acc;
-        }
+      for (int ks = 0; ks < kWy / 4; ++ks) {
+        const int i = 4 * ks + g;   // this lane's k
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vs[i][16 * w + q], w2[i][q],
+                                                   acc, 0, 0, 0);
+      }
+      const int c = k0 + q;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + 16 * w + g + 4 * e;
+        if (r < N && c < N) Z[(size_t)r * N + c] -= acc[e];
       }
       __syncthreads();
     }
