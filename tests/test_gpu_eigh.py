@@ -278,6 +278,35 @@ def test_eigh_serving_bitwise(sca):
             assert res[f] == res_a[f], (k, f)
 
 
+def test_eigh_mixed_routes_in_one_server(sca):
+    """Spectral, pivoted-LU and FP32-refined requests of the same shapes in
+    one server form separate groups (the route is part of a group's key);
+    every result still equals its own sca.adam_solve bit for bit."""
+    import torch
+    from paper_2311_04435_amd.serve import Server
+    reqs = []
+    for k in range(6):
+        r = synth.uniform(3600 + k, 3, 0.0, 1.0)
+        route = [dict(factor="eigh"), dict(factor="lu"),
+                 dict(factor="lu", precision="fp32r")][k % 3]
+        p = sca.Params(L=12, U=3.0 + 2.0 * r[0], delta=r[1],
+                       T=0.1 + 0.1 * r[2], n_max=32, **route)
+        reqs.append(dict(params=p,
+                         phi0=cuda(synth.uniform(3700 + k, 144, -0.5, 0.5)),
+                         n_steps=4 + k))
+    with Server(max_batch=4) as srv:
+        tickets = [srv.submit(r["params"], r["phi0"], r["n_steps"], lr=0.02)
+                   for r in reqs]
+        done = srv.drain(tickets)
+    for k, r in enumerate(reqs):
+        phi, m, v, res, _ = done[tickets[k]]
+        phi_a, m_a, v_a, res_a = sca.adam_solve(r["params"], r["phi0"],
+                                                r["n_steps"], lr=0.02)
+        assert torch.equal(phi, phi_a), k
+        assert torch.equal(m, m_a) and torch.equal(v, v_a), k
+        assert res["omega_tilde"] == res_a["omega_tilde"], k
+
+
 def test_eigh_autograd(sca):
     import torch
     from paper_2311_04435_amd.autograd import potential
