@@ -15,7 +15,7 @@ Prints one JSON line.  Besides the contract fields it carries
                 profiled run of the same steps;
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample;
   l32           steps/s of the 32x32 ionic lattice: FP32 refined, FP64
-                pivoted LU, FP64 symmetric L D L^T;
+                pivoted LU, FP64 symmetric L D L^T, FP64 spectral;
   symmetric_ldlt the same workload on the symmetric route (unpivoted
                 L D L^T, exact for these complex symmetric matrices, half
                 the flops) with its own roofline;
@@ -455,7 +455,9 @@ def main():
         out["l32"] = [workload_rate(sca, "ionic_32x32_U4", "fp32r", 5, 1),
                       workload_rate(sca, "ionic_32x32_U4", "fp64", 3, 1),
                       workload_rate(sca, "ionic_32x32_U4", "fp64", 5, 1,
-                                    "ldlt")]
+                                    "ldlt"),
+                      workload_rate(sca, "ionic_32x32_U4", "fp64", 20, 2,
+                                    "eigh")]
     if args.factor == "lu" and prec == "fp64" and not args.no_symmetric:
         # the same workload on the symmetric route (unpivoted L D L^T)
         out["symmetric_ldlt"] = route_line(sca, args.workload, "fp64", "ldlt",
