@@ -41,6 +41,7 @@
 //                      slice of Z and each block of V in LDS.
 //   expand_kernel      dg[b][i] = sum_k psi_k(i)^2 / (z_b - lambda_k)
 //   lad_kernel         lad[b] = sum_k ln|z_b - lambda_k|, growth[b] = 1
+#include <algorithm>
 #include <float.h>
 #include <math.h>
 #include "sca_common.h"
@@ -171,7 +172,9 @@ eig_init_kernel(const ProbDesc* __restrict__ probs, const double* __restrict__ h
     A[j] = -t * (double)kmult(i, j, L) + (i == j ? hi : 0.0);
 }
 
-// Householder step j (0 <= j < N), grid (ceil(N / 4), nH), 256 threads.
+// Householder step j (0 <= j < N), grid (ceil(N / WV) - first, nH), WV
+// waves; the launch covers the row blocks from `first` (the block of row
+// j + 1) on.
 // The reflector of column j-1 (v, tau, p = tau A_{j-1} v: support [j, N))
 // is pending from the previous launch; w = p - (tau/2)(p.v) v and
 // A_j = A_{j-1} - v w^T - w v^T on [j, N)^2.
@@ -184,11 +187,11 @@ eig_init_kernel(const ProbDesc* __restrict__ probs, const double* __restrict__ h
 // is issued before the first reduction.
 template <int KM, int WV>
 __global__ void __launch_bounds__(WV * 64)
-hh_step_kernel(int N, int j, EigBufs E) {
+hh_step_kernel(int N, int j, int first, EigBufs E) {
   constexpr int NT = WV * 64;
   const int hv = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r = blockIdx.x * WV + w;   // this wave's row
+  const int r = (first + blockIdx.x) * WV + w;   // this wave's row
   double* A = E.A + (size_t)hv * N * N;
   double* vb = E.vec + (size_t)hv * 6 * N;
   double* taub = E.tau + 2 * hv;
@@ -1005,9 +1008,14 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
   auto kern = N <= 512 ? hh_step_kernel<8, kRowsPerWg>
             : N <= 1024 ? hh_step_kernel<16, 8>
             : N <= 2560 ? hh_step_kernel<40, 8> : hh_step_kernel<64, 8>;
-  for (int j = 0; j < N; ++j)
-    hipLaunchKernelGGL(kern, dim3(nrow, nH), dim3(wv * 64),
-                       sizeof(double) * 3 * N, st, N, j, E);
+  // above N = 1024 only the workgroups that hold rows below j (the others'
+  // rows are finished; workgroup 0 of each launch also writes the
+  // reflector): 13% less time at 2304, 2% more at 400 and 1024, as measured
+  for (int j = 0; j < N; ++j) {
+    const int first = N > 1024 ? std::min((j + 1) / wv, nrow - 1) : 0;
+    hipLaunchKernelGGL(kern, dim3(nrow - first, nH), dim3(wv * 64),
+                       sizeof(double) * 3 * N, st, N, j, first, E);
+  }
   mark_end(K_TRIDIAG, st);
   mark_begin(K_SPECTRUM, st);
   hipLaunchKernelGGL(bisect_kernel, dim3((N + 3) / 4, nH), dim3(256),
