@@ -29,8 +29,8 @@
 //                      eigenvalue with the block of T and the factors in
 //                      LDS, the same arithmetic).
 //   mgs_kernel         eigenvalues of one block closer than 1e-4 |T_blk| form
-//                      a cluster; its vectors are orthonormalised (modified
-//                      Gram-Schmidt, two passes) in index order.
+//                      a cluster; its vectors are orthonormalised in index
+//                      order (block Gram-Schmidt over rows, two passes).
 //   wy_t_kernel        compact WY factor T of each block of 32 reflectors:
 //                      H_j0 .. H_j0+31 = I - V T V^T (Schreiber & Van Loan)
 //   wy_apply_kernel    psi = Q Z in place: the blocks applied to Z from the
@@ -644,7 +644,13 @@ invit_lds_kernel(int N, EigBufs E) {
 }
 
 // grid (ceil(N / 4), nH), 256 threads: the wave of eigenvalue t acts if t
-// starts a cluster of two or more inside its block.
+// starts a cluster of two or more inside its block.  The cluster's vectors
+// are the columns t .. c1-1 of Z, contiguous inside each row, so the wave
+// works on rows (lane l takes rows b0 + l + 64 k): each vector jc is made
+// orthogonal to the earlier ones in chunks of kMgsChunk (one pass over the
+// rows forms the chunk's dot products, a second subtracts the projections:
+// block Gram-Schmidt), then normalised; the whole is done twice.
+constexpr int kMgsChunk = 16;
 __global__ void __launch_bounds__(256)
 mgs_kernel(int N, EigBufs E) {
   const int hv = blockIdx.y, lane = threadIdx.x & 63;
@@ -661,13 +667,28 @@ mgs_kernel(int N, EigBufs E) {
   double* Z = E.A + (size_t)hv * N * N;
   for (int jc = t + 1; jc < c1; ++jc) {
     for (int pass = 0; pass < 2; ++pass) {
-      for (int q = t; q < jc; ++q) {
-        double dt = 0.0;
-        for (int r = b0 + lane; r < b1; r += 64)
-          dt += Z[(size_t)r * N + jc] * Z[(size_t)r * N + q];
-        dt = wave_sum(dt);
-        for (int r = b0 + lane; r < b1; r += 64)
-          Z[(size_t)r * N + jc] -= dt * Z[(size_t)r * N + q];
+      for (int q0 = t; q0 < jc; q0 += kMgsChunk) {
+        const int nq = min(kMgsChunk, jc - q0);
+        double d[kMgsChunk];
+#pragma unroll
+        for (int i = 0; i < kMgsChunk; ++i) d[i] = 0.0;
+        for (int r = b0 + lane; r < b1; r += 64) {
+          const double* zr = Z + (size_t)r * N;
+          const double x = zr[jc];
+#pragma unroll
+          for (int i = 0; i < kMgsChunk; ++i)
+            if (i < nq) d[i] = fma(x, zr[q0 + i], d[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kMgsChunk; ++i) d[i] = wave_sum(d[i]);
+        for (int r = b0 + lane; r < b1; r += 64) {
+          double* zr = Z + (size_t)r * N;
+          double x = zr[jc];
+#pragma unroll
+          for (int i = 0; i < kMgsChunk; ++i)
+            if (i < nq) x = fma(-d[i], zr[q0 + i], x);
+          zr[jc] = x;
+        }
       }
       double s2 = 0.0;
       for (int r = b0 + lane; r < b1; r += 64) {
