@@ -399,7 +399,6 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     constexpr int CW = rp_chunk(WAVES);
     T yr[RPT][NB], yi[RPT][NB];
     int pos[RPT], org[RPT];
-    T* frow[RPT];   // row of F (re plane; the im plane follows at + plane)
     T* stg = S.xsr + w * rp_stage_per_wave(WAVES);
     __syncthreads();   // the staging overlays LDS the update has read
 #pragma unroll
@@ -409,7 +408,6 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       const bool live = s < RT && p >= c0 && p < Np;
       pos[k] = live ? p : -1;
       org[k] = live ? S.perm[p] : 0;
-      frow[k] = Fr + (size_t)org[k] * Np + c0;
 #pragma unroll
       for (int cb = 0; cb < NB; cb += CW) {
         const int ct = cb >> 4, q0 = cb & 15;
@@ -544,13 +542,46 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
       }
     };
     StaticFor<0, NB>::run(column);
-    // ---- 5. rows to F at their original rows, the diagonal block to LDS,
-    //         positions to perm
+    // ---- 5. rows to F at their original rows, through the wave's LDS
+    //         region CW columns at a time: a store then covers 16 rows x
+    //         2 adjacent columns (one 64-byte run per row) instead of one
+    //         element of 64 different rows
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+#pragma unroll
+      for (int cb = 0; cb < NB; cb += CW) {
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+          stg[2 * (lane * (CW + 1) + c)] = yr[k][cb + c];
+          stg[2 * (lane * (CW + 1) + c) + 1] = yi[k][cb + c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        constexpr int LPR = CW / 2;           // lanes per row
+        constexpr int RPI = 64 / LPR;         // rows per store
+#pragma unroll
+        for (int it = 0; it < 64 / RPI; ++it) {
+          const int src = RPI * it + lane / LPR, cp = 2 * (lane % LPR);
+          const int spos = __shfl(pos[k], src), sorg = __shfl(org[k], src);
+          const T* e = stg + 2 * (src * (CW + 1) + cp);
+          if (spos >= 0) {
+            // even element offsets: two elements form one aligned store
+            typedef T T2 __attribute__((ext_vector_type(2)));
+            T* dst = Fr + (size_t)sorg * Np + c0 + cb + cp;
+            *reinterpret_cast<T2*>(dst) = T2{e[0], e[2]};
+            *reinterpret_cast<T2*>(dst + plane) = T2{e[1], e[3]};
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    // the diagonal block goes to LDS that overlays the staging regions
+    __syncthreads();
+    // the diagonal block to LDS, positions to perm
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       if (pos[k] >= 0) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) { frow[k][c] = yr[k][c]; frow[k][plane + c] = yi[k][c]; }
         if (pos[k] < c0 + NB) {
           const int pr = pos[k] - c0;
 #pragma unroll
