@@ -415,8 +415,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         for (int sl = 0; sl < 4; ++sl) {
           const int ss = 4 * k + sl;
           if (ss < RT) {
-            const int t = w + WAVES * ss;
-            if (t < ntiles && 16 * t + 15 >= c0 && q >= q0 && q < q0 + CW) {
+            if (q >= q0 && q < q0 + CW) {
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 const int r = 16 * sl + M::m(g, i);
@@ -428,12 +427,10 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        if (live) {
 #pragma unroll
-          for (int c = 0; c < CW; ++c) {
-            yr[k][cb + c] = stg[2 * (lane * (CW + 1) + c)];
-            yi[k][cb + c] = stg[2 * (lane * (CW + 1) + c) + 1];
-          }
+        for (int c = 0; c < CW; ++c) {
+          yr[k][cb + c] = stg[2 * (lane * (CW + 1) + c)];
+          yi[k][cb + c] = stg[2 * (lane * (CW + 1) + c) + 1];
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
