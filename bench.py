@@ -60,8 +60,8 @@ HBM_PEAK = 8000.0                       # GB/s
 # counters were taken on: a changed source reports null.
 TRAFFIC = {
     ("lu", "hubbard_20x20_T0.1", "fp64", "lu"): (
-        26.836e9, "k_factor.hip",
-        "3dd260f5648a8bcd175ef014d50ca612e02c05431e78c4a6758f99139d7f7780"),
+        19.410e9, "k_factor.hip",
+        "0fbd7baa06999b7a9c3cd4e6d0f6179584fe9e75c2ec333fec4160fb4bc60807"),
     ("ldlt", "hubbard_20x20_T0.1", "fp64", "ldlt"): (
         8.093e9, "k_ldlt.hip",
         "4cf959a57de490a72fb2705cb64b0f9c8a9a37292161af1ff71b6f28f1ef2ca2"),
