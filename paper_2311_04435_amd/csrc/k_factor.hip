@@ -949,7 +949,8 @@ trtri_kernel(int Np, T* __restrict__ F, const int* __restrict__ perm_g,
       int slo, shi;
       tile_range(I, slo, shi);
       if (slo < shi) load_a(I, slo, 0);   // first half, ahead of the Y products
-      __syncthreads();
+      // xs was last read by the previous step's Y products, which ended at
+      // that step's second barrier: no barrier is needed before writing it
 #pragma unroll
       for (int u = 0; u < XE; ++u) {
         const int e = tid + u * NT;
