@@ -61,7 +61,7 @@ HBM_PEAK = 8000.0                       # GB/s
 TRAFFIC = {
     ("lu", "hubbard_20x20_T0.1", "fp64", "lu"): (
         19.410e9, "k_factor.hip",
-        "2ebdad9c248bd961ea2dfeccae04701ab83a711aab9b7430345c8563a2999089"),
+        "8d8aef049a1a04cccc988f1a194076d2d5c85135afb741865279ef476868a581"),
     ("ldlt", "hubbard_20x20_T0.1", "fp64", "ldlt"): (
         8.093e9, "k_ldlt.hip",
         "4cf959a57de490a72fb2705cb64b0f9c8a9a37292161af1ff71b6f28f1ef2ca2"),

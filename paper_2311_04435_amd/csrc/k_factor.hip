@@ -1075,10 +1075,15 @@ diagdot_kernel(int N, int Np, const T* __restrict__ F,
   }
   const int jl = tid % kDD, part = tid / kDD;
   constexpr int SPP = kDD / kDDParts;      // s values per slice
+  constexpr int EPT = kDD * kDD / 256;     // tile elements per thread
   double accr = 0.0, acci = 0.0;
-  for (int s0 = j0; s0 < Np; s0 += kDD) {
-    __syncthreads();
-    for (int e = tid; e < kDD * kDD; e += 256) {
+  // the tiles of the next s0 are loaded into registers while the current
+  // ones are multiplied from LDS
+  double xr_[EPT], xi_[EPT], yr_[EPT], yi_[EPT];
+  auto load = [&](int s0) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
       const int a = e / kDD, c = e % kDD;
       double x_r = 0.0, x_i = 0.0, y_r = 0.0, y_i = 0.0;
       // W tile: W[perm[j0 + a]][s0 + c]
@@ -1092,10 +1097,21 @@ diagdot_kernel(int N, int Np, const T* __restrict__ F,
         y_r = Fr[(size_t)vrow * Np + j0 + c];
         y_i = Fi[(size_t)vrow * Np + j0 + c];
       }
-      wr[a][c] = x_r; wi[a][c] = x_i;
-      vr[a][c] = y_r; vi[a][c] = y_i;
+      xr_[u] = x_r; xi_[u] = x_i; yr_[u] = y_r; yi_[u] = y_i;
+    }
+  };
+  __syncthreads();                         // wrow, lo
+  load(j0);
+  for (int s0 = j0; s0 < Np; s0 += kDD) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int a = e / kDD, c = e % kDD;
+      wr[a][c] = xr_[u]; wi[a][c] = xi_[u];
+      vr[a][c] = yr_[u]; vi[a][c] = yi_[u];
     }
     __syncthreads();
+    if (s0 + kDD < Np) load(s0 + kDD);
     const int j = j0 + jl;
     const int first = lo[jl];
 #pragma unroll
@@ -1105,11 +1121,12 @@ diagdot_kernel(int N, int Np, const T* __restrict__ F,
       if (s >= first && s < Np) {
         double yr = vr[sl][jl], yi = vi[sl][jl];
         if (s == j) { yr = 1.0; yi = 0.0; }
-        const double xr_ = wr[jl][sl], xi_ = wi[jl][sl];
-        accr += xr_ * yr - xi_ * yi;
-        acci += xr_ * yi + xi_ * yr;
+        const double x_r = wr[jl][sl], x_i = wi[jl][sl];
+        accr += x_r * yr - x_i * yi;
+        acci += x_r * yi + x_i * yr;
       }
     }
+    __syncthreads();                       // the tiles are rewritten next
   }
   pr_s[part][jl] = accr;
   pi_s[part][jl] = acci;
