@@ -60,7 +60,7 @@ HBM_PEAK = 8000.0                       # GB/s
 # counters were taken on: a changed source reports null.
 TRAFFIC = {
     ("lu", "hubbard_20x20_T0.1", "fp64", "lu"): (
-        19.410e9, "k_factor.hip",
+        19.415e9, "k_factor.hip",
         "8d8aef049a1a04cccc988f1a194076d2d5c85135afb741865279ef476868a581"),
     ("ldlt", "hubbard_20x20_T0.1", "fp64", "ldlt"): (
         8.093e9, "k_ldlt.hip",
