@@ -109,10 +109,10 @@ typedef enum { SCA_FACTOR_LU = 0, SCA_FACTOR_LDLT = 1,
  *                     w_{n_c}/3 the truncation error of each term is below
  *                     9^-15 of its scale; a pass above it sets
  *                     SCA_FLAG_TAIL_RANGE (sca_potential and sca_grad then
- *                     re-evaluate without the tail; sca_adam_solve runs the
- *                     remaining steps without it from the check that saw
- *                     the flag; the request server from the next chunk of
- *                     passes).  The same sums are computed, only the
+ *                     re-evaluate without the tail; in sca_adam_solve and
+ *                     the request server that pass applies no update and
+ *                     the solve goes on without the tail from that step:
+ *                     see "Guards of a solve").  The same sums are computed, only the
  *                     evaluation of the high frequencies differs.
  *                     sca_factorize keeps the split it chose in the factor
  *                     buffer and sca_grad_from_factors uses it. */
@@ -135,7 +135,8 @@ typedef struct {
   double lr, beta1, beta2, eps;  /* ADAM (Kingma-Ba) hyper-parameters */
   double grad_tol;     /* stop early once max|g| < grad_tol (0: never) */
   int32_t n_steps;     /* maximum number of ADAM updates */
-  int32_t check_every; /* host reads max|g| every k steps (0: only at end) */
+  int32_t check_every; /* host reads the statistics every k passes (0: by
+                          elapsed time); convergence is tested only if > 0 */
   int32_t t0;          /* ADAM step count already taken (resume); 0 fresh */
   int32_t flags;       /* SCA_ADAM_* bits, 0 by default */
 } sca_adam_opts;
@@ -155,13 +156,25 @@ typedef struct {
 } sca_result;
 
 /* SCA_FLAG_PIVOT_GROWTH: under SCA_FP32_REFINED a factorisation had pivot
- * growth above 1e3; the steps after the check that saw it ran in FP64 when
- * that path is built for N (sca_potential / sca_grad re-run in FP64 by
- * themselves, or return SCA_ENUMERIC when it is not). */
+ * growth max|u|/max|a| above the context's limit (SCA_OPT_FP32_GROWTH_LIMIT,
+ * 1e3 by default).  Where an FP64 path is built for N (L*L <= 1024) the
+ * pass that saw it applies no update and the solve continues in FP64 from
+ * that step (sca_potential, sca_grad and sca_factorize redo the evaluation
+ * in FP64); where it is not, sca_adam_solve and the server report the flag
+ * and sca_potential / sca_grad / sca_factorize return SCA_ENUMERIC. */
 #define SCA_FLAG_NONFINITE 1    /* a non-finite value was produced */
 #define SCA_FLAG_PIVOT_GROWTH 2 /* FP32 growth above 1e3 (see above) */
 #define SCA_FLAG_CONVERGED 4    /* stopped by grad_tol */
 #define SCA_FLAG_TAIL_RANGE 8   /* a pass exceeded the tail's spectral guard */
+
+/* Guards of a solve.  Every pass of sca_adam_solve checks on the device,
+ * before its update, the Gershgorin bound of the tail (SCA_TAIL_MOMENTS)
+ * and, under SCA_FP32_REFINED, the pivot growth; a pass that fails either
+ * applies no update and advances no step counter, and the host re-plans
+ * the problem (every frequency; FP64) when it next reads the statistics
+ * and resumes from the step that was held back.  The trajectory is
+ * therefore the same as with the switch made at that very step, whatever
+ * check_every is and whoever shares a server's batches. */
 
 /* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`
  * (a hipStream_t; NULL = the null stream).  hbm_budget_bytes bounds the
@@ -171,23 +184,43 @@ SCA_API sca_status sca_create(int device, void* hip_stream, size_t hbm_budget_by
                       sca_ctx** out);
 SCA_API void sca_destroy(sca_ctx* ctx);
 
+/* Context options (sca_set_option; SCA_EINVAL for an unknown option or an
+ * invalid value).
+ *   SCA_OPT_FP32_GROWTH_LIMIT  pivot growth above which a complex64 LU is
+ *                              not trusted (see SCA_FLAG_PIVOT_GROWTH);
+ *                              finite, >= 1; default 1e3. */
+#define SCA_OPT_FP32_GROWTH_LIMIT 1
+SCA_API sca_status sca_set_option(sca_ctx* ctx, int32_t option, double value);
+
 /* Device workspace (bytes) one problem needs: admission control for
  * serving.  0 if the parameters are invalid. */
 SCA_API size_t sca_footprint_bytes(const sca_params* p);
 
-/* Omega and Omega~ (Eq. (7)) at phi[N] -> omega2[2] = {Omega, Omega~}. */
+/* Omega and Omega~ at phi[N] -> omega2[2] = {Omega, Omega~}: the SCA
+ * potential V(phi) of Eq. (7) (Sec. II), with the sum over the Matsubara
+ * frequencies cut at n_max. */
 SCA_API sca_status sca_potential(sca_ctx* ctx, const sca_params* p, const double* phi,
                          double* omega2);
 
-/* Gradient dOmega/dphi -> grad[N]; omega2[2] as above, or NULL. */
+/* Gradient dOmega/dphi -> grad[N]; omega2[2] as above, or NULL.  The
+ * derivative of Eq. (7): d ln det A / d phi_i = -s (A^-1)_ii for the
+ * diagonal coupling -s phi_i of H_s (Eq. (5) after the static
+ * Hubbard-Stratonovich decoupling), which the paper takes by automatic
+ * differentiation (Sec. III). */
 SCA_API sca_status sca_grad(sca_ctx* ctx, const sca_params* p, const double* phi,
                     double* grad, double* omega2);
 
 /* ADAM minimisation of Omega from phi (in: phi0, out: final phi), with the
  * first and second moments m[N], v[N] (in/out, zeros for a fresh start) so a
- * run can resume where another stopped (opts->t0 = steps already taken).
- * Every step runs on the device; the host only polls max|g| every
- * check_every steps when grad_tol > 0.  res is filled on success. */
+ * run can resume where another stopped (opts->t0 = steps already taken):
+ * the optimiser the paper applies to Eq. (7) (Sec. II after Eq. (7), and
+ * Sec. III), Kingma-Ba with bias correction.  Every step runs on the
+ * device; the host reads the statistics of the last pass every check_every
+ * passes (0: every ~50 ms of passes), acts on the guards above and, with
+ * grad_tol > 0 and check_every > 0, stops once max|g| < grad_tol.
+ * res->max_pivot_growth is the largest over the whole call; steps_done the
+ * updates applied.  On SCA_ENUMERIC (a non-finite value) phi, m, v hold
+ * the state the failing pass produced and res->steps_done says when. */
 SCA_API sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
                           const sca_adam_opts* opts, double* phi, double* m,
                           double* v, sca_result* res);
@@ -216,20 +249,34 @@ SCA_API sca_status sca_hmc(sca_ctx* ctx, const sca_params* p,
                            const double* momenta, const double* uniforms,
                            int32_t* accepted, double* h_old, double* h_new);
 
-/* Density of states per spin (Eq. (8), mu = 0): rho[2][n_w] (spin up first)
- * at the n_w real frequencies w[n_w], broadening eta > 0. */
+/* Matsubara frequencies per spin that the calls above factorise for p at
+ * phi (device array of N) -> *n_factorised (host): n_max, or under
+ * SCA_TAIL_MOMENTS the split n_c described there, planned from max|phi|
+ * and max|onsite| read on the device (SCA_ENUMERIC if either is not
+ * finite).  The frequencies above n_c enter Eq. (7) through the moment
+ * series of the same sums. */
+SCA_API sca_status sca_tail_split(sca_ctx* ctx, const sca_params* p,
+                                  const double* phi, int32_t* n_factorised);
+
+/* Density of states per spin (Eq. (8), mu = 0; the spectral function of
+ * the optimised field, Sec. II): rho[2][n_w] (spin up first) at the n_w
+ * real frequencies w[n_w], broadening eta > 0. */
 SCA_API sca_status sca_dos(sca_ctx* ctx, const sca_params* p, const double* phi,
                    const double* w, int32_t n_w, double eta, double* rho);
 
 /* The per-matrix terms behind the calls above, for arbitrary complex shifts
  * z[n_z][2] (re, im): for both spins (up first) and every z_j,
- *   logabsdet[2][n_z] = ln|det(z_j I - H_s)|
- *   diag[2][n_z][N][2] = (z_j I - H_s)^-1_ii  (re, im interleaved). */
+ *   logabsdet[2][n_z] = ln|det(z_j I - H_s)|   (the ln det of Eq. (7) at
+ *                       z = i w_n, of Eq. (8) at z = w + i eta)
+ *   diag[2][n_z][N][2] = (z_j I - H_s)^-1_ii  (re, im interleaved; the
+ *                       gradient's and the DOS's term). */
 SCA_API sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
                              const double* phi, const double* z, int32_t n_z,
                              double* logabsdet, double* diag);
 
-/* Differentiable split of sca_grad (a custom autograd backward): the
+/* Differentiable split of sca_grad (a custom autograd backward of Eq. (7),
+ * in place of the automatic differentiation of the determinant the paper
+ * uses in Sec. III): the
  * forward factorises every A_ns and keeps what the backward needs in the
  * caller's device buffer `factors` of sca_factor_bytes(p) bytes (0 for
  * invalid params); the backward then reads it instead of factorising
@@ -238,7 +285,10 @@ SCA_API sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
  * second sca_grad_from_factors on the same buffer returns SCA_EINVAL until
  * sca_factorize refills it; the other paths leave the buffer reusable.  A
  * buffer that sca_factorize did not fill for these params is refused with
- * SCA_EINVAL. */
+ * SCA_EINVAL.  Under SCA_FP32_REFINED the buffer has room for FP64 factors
+ * too: a factorisation whose pivot growth exceeds the context's limit is
+ * redone in FP64 (SCA_ENUMERIC where no FP64 path is built), and the
+ * backward uses whichever was kept. */
 SCA_API size_t sca_factor_bytes(const sca_params* p);
 SCA_API sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
                          void* factors, double* omega2);
@@ -313,7 +363,9 @@ SCA_API sca_status sca_profile_read(sca_ctx* ctx, double* total_ms,
  *                       Reports the running and queued request counts.
  *   sca_server_poll     *done = 1 once the request finished; then *res
  *                       (flags as for sca_adam_solve; a pivot growth above
- *                       1e3 under FP32 is flagged, not re-run) and *t_done
+ *                       1e3 under FP32 is flagged, not re-run; a tail
+ *                       member whose guard fires continues with every
+ *                       frequency from the step that was held back) and *t_done
  *                       (sca_server_clock time the server saw it finish)
  *                       are set and the ticket is released.
  *   sca_server_clock    seconds since the server was created. */

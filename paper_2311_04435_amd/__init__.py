@@ -21,7 +21,8 @@ import torch
 from . import _lib
 from ._lib import (SCAError, SCA_FP64, SCA_FP32_REFINED,  # noqa: F401
                    SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH,
-                   SCA_FLAG_CONVERGED, SCA_FLAG_TAIL_RANGE)
+                   SCA_FLAG_CONVERGED, SCA_FLAG_TAIL_RANGE,
+                   SCA_OPT_FP32_GROWTH_LIMIT)
 
 PRECISIONS = {"fp64": SCA_FP64, "fp32r": SCA_FP32_REFINED}
 FACTORS = {"lu": _lib.SCA_FACTOR_LU, "ldlt": _lib.SCA_FACTOR_LDLT,
@@ -198,6 +199,19 @@ class Context:
             z.data_ptr(), n_z, lad.data_ptr(), dg.data_ptr()))
         return lad, torch.view_as_complex(dg)
 
+    def set_option(self, option: int, value: float):
+        """sca_set_option, e.g. (SCA_OPT_FP32_GROWTH_LIMIT, 1e3)."""
+        _lib.check(_lib.lib.sca_set_option(self._h, option, float(value)))
+
+    def tail_split(self, p: Params, phi: torch.Tensor) -> int:
+        """Matsubara frequencies per spin the library factorises for p at
+        phi (n_max without the tail)."""
+        n = C.c_int32()
+        _lib.check(_lib.lib.sca_tail_split(self._h, C.byref(p.c()),
+                                           _dev(phi, p.N, "phi").data_ptr(),
+                                           C.byref(n)))
+        return int(n.value)
+
     def profile(self, enable: bool = True):
         """Start (reset) or stop per-kernel HIP-event timing."""
         _lib.check(_lib.lib.sca_profile(self._h, 1 if enable else 0))
@@ -268,15 +282,8 @@ def adam_solve(p: Params, phi0: torch.Tensor, n_steps: int, **kw):
 
 def tail_split(p: Params, phi: torch.Tensor) -> int:
     """Number of Matsubara frequencies the library factorises for p at phi
-    under Params(tail=True) (the rule of include/sca.h, SCA_TAIL_MOMENTS)."""
-    import math
-    if not p.tail:
-        return p.n_max
-    pmax = float(phi.abs().max())
-    omax = float(p.onsite.abs().max()) if p.onsite is not None else 0.0
-    rho = 4 * abs(p.t) + 0.5 * abs(p.delta) + omax + max(pmax, 0.5 * p.U) + 0.5
-    x = (4 * rho / (math.pi * p.T) - 1) / 2
-    return p.n_max if x >= p.n_max else max(1, math.ceil(x))
+    (sca_tail_split: n_max, or the SCA_TAIL_MOMENTS split)."""
+    return default_context().tail_split(p, phi)
 
 
 def hmc(p: Params, phi0: torch.Tensor, momenta: torch.Tensor, uniforms,

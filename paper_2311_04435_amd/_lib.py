@@ -21,6 +21,7 @@ SCA_FLAG_NONFINITE, SCA_FLAG_PIVOT_GROWTH, SCA_FLAG_CONVERGED = 1, 2, 4
 SCA_FLAG_TAIL_RANGE = 8
 SCA_TAIL_NONE, SCA_TAIL_MOMENTS = 0, 1
 SCA_ADAM_NO_FINAL_EVAL = 1
+SCA_OPT_FP32_GROWTH_LIMIT = 1
 PROFILE_SLOTS = 16
 KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
                   "refine", "wvgemm", "ldlt", "trtri_sym", "symdiag",
@@ -29,7 +30,7 @@ KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
 # Every symbol include/sca.h declares.
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",
            "sca_grad", "sca_adam_solve", "sca_hmc", "sca_dos",
-           "sca_shifted_terms",
+           "sca_shifted_terms", "sca_tail_split", "sca_set_option",
            "sca_factor_bytes", "sca_factorize", "sca_grad_from_factors",
            "sca_profile", "sca_profile_read", "sca_server_create",
            "sca_server_destroy", "sca_server_clock", "sca_server_submit",
@@ -90,6 +91,8 @@ def _load():
                           C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "sca_dos": (i32, [vp, P, dp, dp, i32, C.c_double, dp]),
         "sca_shifted_terms": (i32, [vp, P, dp, dp, i32, dp, dp]),
+        "sca_tail_split": (i32, [vp, P, dp, C.POINTER(i32)]),
+        "sca_set_option": (i32, [vp, i32, C.c_double]),
         "sca_factor_bytes": (C.c_size_t, [P]),
         "sca_factorize": (i32, [vp, P, dp, vp, dp]),
         "sca_grad_from_factors": (i32, [vp, P, dp, vp, dp]),

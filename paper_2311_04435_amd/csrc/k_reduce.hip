@@ -77,14 +77,54 @@ struct ChunkPartial {
   double phi2;      // sum phi_i^2 (phi at which the terms were evaluated)
   double stag;      // sum (-1)^(x+y) phi_i
   double gmax;      // max |g_i|
-  double hmax;      // max_i max_s |h_i| (Gershgorin bound of the tail guard)
   double kin0, kin; // HMC: sum p^2 before / after the kick
-  int32_t nonfinite, pad_;
+  int32_t nonfinite;
+  int32_t guard;    // kGuard* bits of the pass (the same in every chunk)
 };
+
+// Guard bits of a pass (see ProbDesc): the Gershgorin bound 4|t| +
+// max_i (|Delta/2 + onsite_i| + |phi_i|) of H against tail_guard, and the
+// largest pivot growth of the problem's matrices against growth_limit.
+// Block-wide; every block of the problem computes the same bits (max is
+// exact in any order, and a NaN stays a NaN).
+__device__ int pass_guard(const ProbDesc& P, const double* __restrict__ growth,
+                          double (*red)[kReduceThreads]) {
+  const int tid = threadIdx.x;
+  const bool tail = P.Me < P.M;
+  const bool grow = P.growth_limit > 0.0 && growth != nullptr;
+  if (!tail && !grow) return 0;
+  double hm = 0.0, gm = 0.0;
+  if (tail)
+    for (int k = tid; k < P.N; k += kReduceThreads) {
+      double a = 0.5 * P.delta * (double)stagger_sign(k, P.L);
+      if (P.onsite) a += P.onsite[k];
+      hm = max_nan(hm, fabs(a) + fabs(P.phi[k]));
+    }
+  if (grow)
+    for (int k = tid; k < 2 * P.Me; k += kReduceThreads)
+      gm = max_nan(gm, growth[P.mat_begin + k]);
+  red[0][tid] = hm;
+  red[1][tid] = gm;
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w >= 1; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] = max_nan(red[0][tid], red[0][tid + w]);
+      red[1][tid] = max_nan(red[1][tid], red[1][tid + w]);
+    }
+    __syncthreads();
+  }
+  int guard = 0;
+  if (tail && !(red[0][0] + 4.0 * fabs(P.t) <= P.tail_guard))
+    guard |= kGuardTail;
+  if (grow && !(red[1][0] <= P.growth_limit)) guard |= kGuardGrowth;
+  return guard;
+}
 
 __global__ void __launch_bounds__(kReduceThreads)
 site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
-                   const double* __restrict__ dg, ChunkPartial* __restrict__ part,
+                   const double* __restrict__ dg,
+                   const double* __restrict__ growth,
+                   ChunkPartial* __restrict__ part,
                    int adam, const double* __restrict__ mom,
                    const double* __restrict__ tsum, int hmc) {
   const int p = blockIdx.y;
@@ -95,8 +135,10 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
   const int bpart = tid / kSitesPerBlock;
   const int i = chunk * kSitesPerBlock + site_l;
   __shared__ double acc_s[kBParts][kSitesPerBlock];
-  __shared__ double red_s[6][kSitesPerBlock];
+  __shared__ double red_s[5][kSitesPerBlock];
   __shared__ int nf_s[kSitesPerBlock];
+  __shared__ double guard_s[2][kReduceThreads];
+  const int guard = pass_guard(P, growth, guard_s);
 
   // sum over the problem's 2 Me matrices, split in kBParts contiguous ranges
   // per spin; each range summed in increasing n
@@ -115,17 +157,12 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
   acc_s[bpart][site_l] = acc;
   __syncthreads();
   if (bpart == 0) {
-    double phi2 = 0.0, stag = 0.0, ga = 0.0, hm = 0.0, k0 = 0.0, k1 = 0.0;
+    double phi2 = 0.0, stag = 0.0, ga = 0.0, k0 = 0.0, k1 = 0.0;
     int nf = 0;
     if (i < N) {
       double s = acc_s[0][site_l];
       for (int q = 1; q < kBParts; ++q) s += acc_s[q][site_l];
       const double ph = P.phi[i];
-      if (P.Me < P.M) {
-        double a = 0.5 * P.delta * (double)stagger_sign(i, P.L);
-        if (P.onsite) a += P.onsite[i];
-        hm = fabs(a) + fabs(ph);
-      }
       if (P.Me < P.M && dg) {
         // tail: sum_{n >= Me} Re G_ii = -sum_m (-1)^m (H^(2m+1))_ii S_{2m+2},
         // up minus down
@@ -162,7 +199,7 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
           P.phi_out[i] = nphi;
         }
       }
-      if (adam && dg && P.steps_left > 0) {
+      if (adam && dg && P.steps_left > 0 && !guard) {
         const int t = P.adam_t + 1;
         const double m = P.beta1 * P.m[i] + (1.0 - P.beta1) * g;
         const double v = P.beta2 * P.v[i] + (1.0 - P.beta2) * g * g;
@@ -179,27 +216,25 @@ site_reduce_kernel(const ProbDesc* __restrict__ probs, int N,
     red_s[0][site_l] = phi2;
     red_s[1][site_l] = stag;
     red_s[2][site_l] = ga;
-    red_s[3][site_l] = hm;
-    red_s[4][site_l] = k0;
-    red_s[5][site_l] = k1;
+    red_s[3][site_l] = k0;
+    red_s[4][site_l] = k1;
     nf_s[site_l] = nf;
   }
   __syncthreads();
   if (tid == 0) {
-    double a = 0.0, b = 0.0, c = 0.0, h = 0.0, k0 = 0.0, k1 = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0, k0 = 0.0, k1 = 0.0;
     int nf = 0;
     for (int q = 0; q < kSitesPerBlock; ++q) {
       a += red_s[0][q];
       b += red_s[1][q];
-      c = fmax(c, red_s[2][q]);
-      h = fmax(h, red_s[3][q]);
-      k0 += red_s[4][q];
-      k1 += red_s[5][q];
+      c = max_nan(c, red_s[2][q]);
+      k0 += red_s[3][q];
+      k1 += red_s[4][q];
       nf |= nf_s[q];
     }
     ChunkPartial cp;
-    cp.phi2 = a; cp.stag = b; cp.gmax = c; cp.hmax = h; cp.kin0 = k0; cp.kin = k1;
-    cp.nonfinite = nf; cp.pad_ = 0;
+    cp.phi2 = a; cp.stag = b; cp.gmax = c; cp.kin0 = k0; cp.kin = k1;
+    cp.nonfinite = nf; cp.guard = guard;
     part[p * kMaxChunks + chunk] = cp;
   }
 }
@@ -224,7 +259,7 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
     const double l = lad[P.mat_begin + k];
     full += l;
     red += l - (double)N * log(w);
-    gr = fmax(gr, growth[P.mat_begin + k]);
+    gr = max_nan(gr, growth[P.mat_begin + k]);
   }
   if (P.Me < P.M) {
     // tail of both spins: 1/2 sum_m (-1)^(m+1)/m tr(H^2m) S_2m, plus
@@ -248,20 +283,20 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
     if (tid < w) {
       s_full[tid] += s_full[tid + w];
       s_red[tid] += s_red[tid + w];
-      s_gr[tid] = fmax(s_gr[tid], s_gr[tid + w]);
+      s_gr[tid] = max_nan(s_gr[tid], s_gr[tid + w]);
     }
     __syncthreads();
   }
   if (tid == 0) {
-    double phi2 = 0.0, stag = 0.0, gmax = 0.0, hmax = 0.0, k0 = 0.0, k1 = 0.0;
+    double phi2 = 0.0, stag = 0.0, gmax = 0.0, k0 = 0.0, k1 = 0.0;
     int nf = 0;
     for (int c = 0; c < nchunks; ++c) {
       const ChunkPartial cp = part[p * kMaxChunks + c];
-      phi2 += cp.phi2; stag += cp.stag; gmax = fmax(gmax, cp.gmax);
-      hmax = fmax(hmax, cp.hmax);
+      phi2 += cp.phi2; stag += cp.stag; gmax = max_nan(gmax, cp.gmax);
       k0 += cp.kin0; k1 += cp.kin;
       nf |= cp.nonfinite;
     }
+    const int guard = part[p * kMaxChunks].guard;
     ProbStats S;
     S.omega = phi2 / P.U - 2.0 * P.T * s_full[0];
     S.omega_tilde = phi2 / P.U - 2.0 * P.T * s_red[0];
@@ -270,14 +305,22 @@ problem_reduce_kernel(ProbDesc* __restrict__ probs, int N,
     S.pivot_growth = s_gr[0];
     nf |= !isfinite(S.omega) || !isfinite(S.omega_tilde);
     S.nonfinite = nf;
-    S.tail_range = (P.Me < P.M && !(hmax + 4.0 * fabs(P.t) <= P.tail_guard)) ? 1 : 0;
+    S.tail_range = (guard & kGuardTail) ? 1 : 0;
     S.kin0 = 0.5 * k0;
     S.kin = 0.5 * k1;
+    S.growth_run = max_nan(P.growth_run, s_gr[0]);
+    S.guard = guard;
+    // the site kernel of this pass has read adam_t and steps_left already;
+    // it applied the update exactly when the same condition held
+    const bool upd = advance && P.steps_left > 0 && !guard;
+    S.updated = upd ? 1 : 0;
+    S.adam_t = P.adam_t + (upd ? 1 : 0);
+    S.steps_left = P.steps_left - (upd ? 1 : 0);
     stats[p] = S;
-    // the site kernel of this pass has read adam_t and steps_left already
-    if (advance && P.steps_left > 0) {
-      probs[p].adam_t = P.adam_t + 1;
-      probs[p].steps_left = P.steps_left - 1;
+    probs[p].growth_run = S.growth_run;
+    if (upd) {
+      probs[p].adam_t = S.adam_t;
+      probs[p].steps_left = S.steps_left;
     }
     if (hmc && P.hmc_L > 0) probs[p].hmc_k = P.hmc_k + 1;
   }
@@ -300,7 +343,7 @@ hipError_t launch_reduce(ProbDesc* probs, int nprob, int N, const double* lad,
   ChunkPartial* part = static_cast<ChunkPartial*>(ws);
   mark_begin(K_REDUCE, st);
   hipLaunchKernelGGL(site_reduce_kernel, dim3(nchunks, nprob),
-                     dim3(kReduceThreads), 0, st, probs, N, dg, part,
+                     dim3(kReduceThreads), 0, st, probs, N, dg, growth, part,
                      (int)adam, mom, tsum, (int)(hmc && dg != nullptr));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -87,11 +87,11 @@ __global__ void __launch_bounds__(256)
 absmax_kernel(const double* __restrict__ x, int n, double* __restrict__ out) {
   __shared__ double r[256];
   double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(x[i]));
+  for (int i = threadIdx.x; i < n; i += 256) m = max_nan(m, fabs(x[i]));
   r[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
-    if (threadIdx.x < w) r[threadIdx.x] = fmax(r[threadIdx.x], r[threadIdx.x + w]);
+    if (threadIdx.x < w) r[threadIdx.x] = max_nan(r[threadIdx.x], r[threadIdx.x + w]);
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = r[0];

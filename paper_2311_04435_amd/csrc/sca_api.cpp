@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -51,6 +52,7 @@ struct sca_ctx {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   double* dscalar = nullptr;   // one device double (tail planning)
+  double growth_limit = 1e3;   // SCA_OPT_FP32_GROWTH_LIMIT
   sca::Profiler prof;
 };
 
@@ -350,13 +352,19 @@ sca_status begin_call(sca_ctx* ctx, const sca_params* p) {
   return check_dev_ptr(ctx, p->onsite, "params.onsite", true);
 }
 
-// Pivot growth above which a complex64 factorisation is not trusted: the
-// backward error of an LU grows with it, and the FP64 refinement only
-// corrects an error of FP32 size.
-constexpr double kFp32GrowthMax = 1e3;
+// Pivot growth above which a complex64 factorisation is not trusted (the
+// context's SCA_OPT_FP32_GROWTH_LIMIT, 1e3 by default): the backward error
+// of an LU grows with it, and the FP64 refinement only corrects an error of
+// FP32 size.
+bool growth_exceeded(const sca_ctx* ctx, int mode, double growth) {
+  return (mode & kModeFp32) && !(growth <= ctx->growth_limit);
+}
 
-bool growth_exceeded(int mode, double growth) {
-  return (mode & kModeFp32) && !(growth <= kFp32GrowthMax);
+// The limit a pass of route `mode` checks on the device: the context's, if
+// an FP64 route can take over for N, else 0 (the growth is only reported).
+double device_growth_limit(const sca_ctx* ctx, int N, int mode) {
+  return ((mode & kModeFp32) && path_supported(N, mode & ~kModeFp32))
+             ? ctx->growth_limit : 0.0;
 }
 
 sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
@@ -365,6 +373,7 @@ sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
   ProbDesc P = make_prob(p, phi, grad);
   sca_status s = plan_tail(ctx, p, phi, P);
   if (s) return s;
+  P.growth_limit = device_growth_limit(ctx, N, route_of(p));
   const int B = 2 * P.Me;
   Carve c0 = carve(nullptr, 1, N, B, route_of(p), true, true,
                    factor_workspace_bytes(N, B, route_of(p)));
@@ -383,10 +392,10 @@ sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
     q.tail = SCA_TAIL_NONE;
     return eval_single(ctx, &q, phi, grad, omega2, st_out);
   }
-  if (growth_exceeded(route_of(p), S.pivot_growth) && !S.nonfinite) {
+  if (growth_exceeded(ctx, route_of(p), S.pivot_growth)) {
     if (!path_supported(N, route_of(p) & ~kModeFp32))
-      return fail(SCA_ENUMERIC, "FP32 pivot growth %.3g above %.0e and no "
-                  "FP64 path for N=%d", S.pivot_growth, kFp32GrowthMax, N);
+      return fail(SCA_ENUMERIC, "FP32 pivot growth %.3g above %.3g and no "
+                  "FP64 path for N=%d", S.pivot_growth, ctx->growth_limit, N);
     sca_params q = *p;
     q.precision = SCA_FP64;
     return eval_single(ctx, &q, phi, grad, omega2, st_out);
@@ -506,74 +515,90 @@ sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
   P.lr = o->lr; P.beta1 = o->beta1; P.beta2 = o->beta2; P.eps = o->eps;
   P.adam_t = o->t0;
   P.steps_left = o->n_steps;
+  P.growth_limit = device_growth_limit(ctx, N, prec);
   std::memset(res, 0, sizeof *res);
-  int done = 0;
+
+  // The passes run in chunks; the host reads the statistics of each chunk's
+  // last pass.  A pass whose guard fires applies no update (the device
+  // counters say how many were applied), so re-planning the problem at the
+  // chunk's end and resuming from the device's step count gives the same
+  // trajectory as a switch at that very pass, whatever the chunk length.
+  const bool final_eval = !(o->flags & SCA_ADAM_NO_FINAL_EVAL);
+  constexpr double kChunkMs = 50.0;   // aim of one chunk when check_every = 0
+  int target = o->n_steps;   // updates to apply (lowered on convergence)
+  int applied = 0;           // updates applied in this call
+  double gmax = 0.0, pass_ms = 0.0;
   bool converged = false, upload = true;
-  for (int k = 1; k <= o->n_steps; ++k) {
-    s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, true, upload);
-    if (s) return s;
-    upload = false;
-    done = k;
-    if (o->check_every > 0 && k % o->check_every == 0) {
-      ProbStats S;
-      if ((s = read_stats(ctx, c, 1, &S))) return s;
-      if (S.nonfinite) {
-        res->steps_done = done;
-        res->flags |= SCA_FLAG_NONFINITE;
-        return fail(SCA_ENUMERIC, "non-finite value at step %d", o->t0 + k);
-      }
-      if (S.tail_range) {
-        // the remaining steps factorise every frequency
-        res->flags |= SCA_FLAG_TAIL_RANGE;
-        P.Me = P.M;
-        P.tail_guard = 0.0;
-        B = 2 * P.M;
-        if ((s = setup())) return s;
-        P.adam_t = o->t0 + done;
-        P.steps_left = o->n_steps - done;
-        upload = true;
-      }
-      if (growth_exceeded(prec, S.pivot_growth)) {
-        // the remaining steps run in FP64 where that path is built
-        res->flags |= SCA_FLAG_PIVOT_GROWTH;
-        if (path_supported(N, prec & ~kModeFp32)) {
-          prec &= ~kModeFp32;
-          if ((s = setup())) return s;
-          P.adam_t = o->t0 + done;
-          P.steps_left = o->n_steps - done;
-          upload = true;
-        }
-      }
-      if (o->grad_tol > 0.0 && S.max_abs_grad < o->grad_tol) {
-        converged = true;
-        break;
-      }
+  ProbStats S{};
+  for (;;) {
+    int need = target - applied + (final_eval ? 1 : 0);
+    if (need < 1) need = 1;
+    int K = need;
+    if (o->check_every > 0) K = std::min(K, o->check_every);
+    else K = std::min(K, pass_ms > 0.0 ? std::max(1, (int)(kChunkMs / pass_ms)) : 1);
+    const auto t_start = std::chrono::steady_clock::now();
+    for (int k = 0; k < K; ++k) {
+      s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, true, upload);
+      if (s) return s;
+      upload = false;
+    }
+    if ((s = read_stats(ctx, c, 1, &S))) return s;
+    pass_ms = 1e3 * std::chrono::duration<double>(
+                        std::chrono::steady_clock::now() - t_start).count() / K;
+    applied = S.adam_t - o->t0;
+    gmax = max_nan(gmax, S.growth_run);
+    if (S.nonfinite) {
+      res->steps_done = applied;
+      res->max_pivot_growth = gmax;
+      res->flags |= SCA_FLAG_NONFINITE;
+      return fail(SCA_ENUMERIC, "non-finite value at step %d", S.adam_t);
+    }
+    if (!converged && o->grad_tol > 0.0 && o->check_every > 0 && S.updated &&
+        S.max_abs_grad < o->grad_tol) {
+      // stop here; with final_eval one more pass evaluates the returned phi
+      converged = true;
+      target = applied;
+      upload = true;
+    }
+    // done: the last pass evaluated the returned phi (final_eval), or
+    // applied the last update (its statistics describe that update's input)
+    const bool done = final_eval
+        ? (applied == target && !S.updated && S.guard == 0)
+        : (applied == target && (S.updated || S.guard == 0));
+    if (done) break;
+    if (S.guard & kGuardTail) {
+      // the remaining steps factorise every frequency
+      res->flags |= SCA_FLAG_TAIL_RANGE;
+      P.Me = P.M;
+      P.tail_guard = 0.0;
+      B = 2 * P.M;
+      if ((s = setup())) return s;
+      upload = true;
+    }
+    if (S.guard & kGuardGrowth) {
+      // the remaining steps run in FP64 (the guard is only armed when that
+      // path is built for N)
+      res->flags |= SCA_FLAG_PIVOT_GROWTH;
+      prec &= ~kModeFp32;
+      P.growth_limit = 0.0;
+      if ((s = setup())) return s;
+      upload = true;
+    }
+    if (upload) {
+      P.adam_t = S.adam_t;
+      P.steps_left = target - applied;
+      P.growth_run = 0.0;
     }
   }
-  ProbStats S;
-  if (o->flags & SCA_ADAM_NO_FINAL_EVAL) {
-    // statistics of the last evaluated phi (input of the final update)
-    if ((s = read_stats(ctx, c, 1, &S))) return s;
-  } else {
-    // statistics at the returned phi
-    s = run_batch(ctx, c, &P, 1, p->L, B, B, prec, false, upload);
-    if (s) return s;
-    if ((s = read_stats(ctx, c, 1, &S))) return s;
-  }
-  if (growth_exceeded(prec, S.pivot_growth))
+  if (growth_exceeded(ctx, route_of(p), gmax))
     res->flags |= SCA_FLAG_PIVOT_GROWTH;
-  if (S.tail_range) res->flags |= SCA_FLAG_TAIL_RANGE;
   res->omega = S.omega;
   res->omega_tilde = S.omega_tilde;
   res->af_order = S.af_order;
   res->max_abs_grad = S.max_abs_grad;
-  res->max_pivot_growth = S.pivot_growth;
-  res->steps_done = done;
+  res->max_pivot_growth = gmax;
+  res->steps_done = applied;
   if (converged) res->flags |= SCA_FLAG_CONVERGED;
-  if (S.nonfinite) {
-    res->flags |= SCA_FLAG_NONFINITE;
-    return fail(SCA_ENUMERIC, "non-finite value in the solve");
-  }
   return SCA_OK;
 }
 
@@ -653,6 +678,19 @@ sca_status sca_hmc(sca_ctx* ctx, const sca_params* p, const sca_hmc_opts* o,
   return SCA_OK;
 }
 
+sca_status sca_tail_split(sca_ctx* ctx, const sca_params* p,
+                          const double* phi, int32_t* n_factorised) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  if (!n_factorised) return fail(SCA_EINVAL, "n_factorised is NULL");
+  DeviceGuard g(ctx, ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  ProbDesc P = make_prob(p, phi, nullptr);
+  if ((s = plan_tail(ctx, p, phi, P))) return s;
+  *n_factorised = P.Me;
+  return SCA_OK;
+}
+
 sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
                              const double* phi, const double* z, int32_t n_z,
                              double* logabsdet, double* diag) {
@@ -726,7 +764,13 @@ size_t sca_factor_bytes(const sca_params* p) {
   g_err = saved;
   if (p->factor == SCA_FACTOR_EIGH) return 0;   // no factors to keep
   const int N = p->L * p->L, B = 2 * p->n_max;
-  return autograd_factor_bytes(N, B, route_of(p));
+  const int mode = route_of(p);
+  size_t bytes = autograd_factor_bytes(N, B, mode);
+  // the FP32 route refactorises in FP64 (same layout up to the factors)
+  // when its pivot growth is too large
+  if ((mode & kModeFp32) && path_supported(N, mode & ~kModeFp32))
+    bytes = std::max(bytes, autograd_factor_bytes(N, B, mode & ~kModeFp32));
+  return bytes;
 }
 
 sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
@@ -747,10 +791,6 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
   Carve c0 = carve(nullptr, 1, N, Be, route_of(p), false, false, 0);
   if ((s = ensure_ws(ctx, c0.total))) return s;
   Carve c = carve((char*)ctx->ws, 1, N, Be, route_of(p), false, false, 0);
-  AutogradLayout lay = autograd_layout(factors, N, B, route_of(p));
-  c.lad = lay.lad;
-  c.dg = lay.dg;
-  c.fact = lay.fact;
   c.tail_on = P.Me < P.M;
   hipStream_t st = ctx->stream;
   if ((s = ensure_pinned(ctx, 512))) return s;
@@ -758,19 +798,31 @@ sca_status sca_factorize(sca_ctx* ctx, const sca_params* p, const double* phi,
   std::memcpy(ctx->pinned, &P, sizeof P);
   FactorHeader* hh = reinterpret_cast<FactorHeader*>(
       static_cast<char*>(ctx->pinned) + 256);
-  *hh = FactorHeader{kFactorsReady, p->L, p->n_max, route_of(p), p->tail,
-                     P.Me, P.tail_guard};
   HIP_TRY(hipMemcpyAsync(c.probs, ctx->pinned, sizeof P, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_matsubara_descs(c.probs, 1, Be, c.descs, st));
   HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
   if (c.tail_on) HIP_TRY(launch_tail(c.probs, 1, N, c.hbuf, c.mom, c.tsum, st));
-  HIP_TRY(factor_forward(c.descs, c.hbuf, Be, N, p->L, route_of(p), c.lad,
-                         c.dg, c.growth, c.fact, st));
-  HIP_TRY(launch_reduce_omega(c.probs, 1, N, c.lad, c.growth, c.stats, c.rws,
-                              c.mom, c.tsum, st));
-  HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice, st));
+  // the FP32 route's factors are redone in FP64 when their pivot growth is
+  // above the context's limit (the header records the route that was kept)
+  int mode = route_of(p);
   ProbStats S;
-  if ((s = read_stats(ctx, c, 1, &S))) return s;
+  for (;;) {
+    AutogradLayout lay = autograd_layout(factors, N, B, mode);
+    HIP_TRY(factor_forward(c.descs, c.hbuf, Be, N, p->L, mode, lay.lad,
+                           lay.dg, lay.growth, lay.fact, st));
+    HIP_TRY(launch_reduce_omega(c.probs, 1, N, lay.lad, lay.growth, c.stats,
+                                c.rws, c.mom, c.tsum, st));
+    if ((s = read_stats(ctx, c, 1, &S))) return s;
+    if (!growth_exceeded(ctx, mode, S.pivot_growth)) break;
+    if (!path_supported(N, mode & ~kModeFp32))
+      return fail(SCA_ENUMERIC, "FP32 pivot growth %.3g above %.3g and no "
+                  "FP64 path for N=%d", S.pivot_growth, ctx->growth_limit, N);
+    mode &= ~kModeFp32;
+  }
+  *hh = FactorHeader{kFactorsReady, p->L, p->n_max, mode, p->tail, P.Me,
+                     P.tail_guard};
+  HIP_TRY(hipMemcpyAsync(autograd_layout(factors, N, B, mode).head, hh,
+                         sizeof *hh, hipMemcpyHostToDevice, st));
   double o2[2] = {S.omega, S.omega_tilde};
   HIP_TRY(hipMemcpyAsync(omega2, o2, sizeof o2, hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -792,24 +844,28 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
   if ((s = check_dev_ptr(ctx, factors, "factors"))) return s;
   if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
   const int N = p->L * p->L, B = 2 * p->n_max;
-  AutogradLayout lay = autograd_layout(factors, N, B, route_of(p));
   ProbDesc P = make_prob(p, phi, grad);
   hipStream_t st = ctx->stream;
   if ((s = ensure_pinned(ctx, 512))) return s;
   HIP_TRY(hipStreamSynchronize(st));
   FactorHeader* hh = reinterpret_cast<FactorHeader*>(
       static_cast<char*>(ctx->pinned) + 256);
-  HIP_TRY(hipMemcpyAsync(hh, lay.head, sizeof *hh, hipMemcpyDeviceToHost, st));
+  // the header sits at the start of every route's layout
+  HIP_TRY(hipMemcpyAsync(hh, factors, sizeof *hh, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (hh->state == kFactorsConsumed)
     return fail(SCA_EINVAL, "factors were consumed by an earlier "
                 "sca_grad_from_factors (this path inverts them in place); "
                 "call sca_factorize again");
+  // the FP32 route may have kept FP64 factors (pivot growth fallback)
+  const int mode = hh->mode;
+  const bool mode_ok = mode == route_of(p) ||
+      ((route_of(p) & kModeFp32) && mode == (route_of(p) & ~kModeFp32));
   if (hh->state != kFactorsReady || hh->L != p->L || hh->n_max != p->n_max ||
-      hh->mode != route_of(p) || hh->tail != p->tail || hh->Me < 1 ||
-      hh->Me > p->n_max)
+      !mode_ok || hh->tail != p->tail || hh->Me < 1 || hh->Me > p->n_max)
     return fail(SCA_EINVAL, "factors do not hold a factorisation of these "
                 "params (sca_factorize not called with them)");
+  AutogradLayout lay = autograd_layout(factors, N, B, mode);
   // the frequencies the forward factorised; the tail again from phi
   P.Me = hh->Me;
   P.tail_guard = hh->tail_guard;
@@ -824,10 +880,10 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
     HIP_TRY(launch_hvec(c.probs, 1, N, c.hbuf, st));
     HIP_TRY(launch_tail(c.probs, 1, N, c.hbuf, c.mom, c.tsum, st));
   }
-  HIP_TRY(factor_backward(Be, N, route_of(p), lay.lad, lay.dg, lay.fact, st));
+  HIP_TRY(factor_backward(Be, N, mode, lay.lad, lay.dg, lay.fact, st));
   HIP_TRY(launch_reduce(c.probs, 1, N, lay.lad, lay.dg, lay.growth, c.stats,
                         false, c.rws, c.mom, c.tsum, st));
-  if (factor_backward_consumes(N, route_of(p))) {
+  if (factor_backward_consumes(N, mode)) {
     hh->state = kFactorsConsumed;
     HIP_TRY(hipMemcpyAsync(lay.head, hh, sizeof *hh, hipMemcpyHostToDevice,
                            st));
@@ -836,6 +892,21 @@ sca_status sca_grad_from_factors(sca_ctx* ctx, const sca_params* p,
   if ((s = read_stats(ctx, c, 1, &S))) return s;
   if (S.nonfinite) return fail(SCA_ENUMERIC, "non-finite gradient");
   return SCA_OK;
+}
+
+sca_status sca_set_option(sca_ctx* ctx, int32_t option, double value) {
+  g_err.clear();
+  if (!ctx) return fail(SCA_EINVAL, "context is NULL");
+  switch (option) {
+    case SCA_OPT_FP32_GROWTH_LIMIT:
+      if (!(value >= 1.0) || !std::isfinite(value))
+        return fail(SCA_EINVAL, "growth limit %g: must be finite and >= 1",
+                    value);
+      ctx->growth_limit = value;
+      return SCA_OK;
+    default:
+      return fail(SCA_EINVAL, "unknown option %d", option);
+  }
 }
 
 sca_status sca_profile(sca_ctx* ctx, int enable) {

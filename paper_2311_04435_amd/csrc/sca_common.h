@@ -45,7 +45,19 @@ struct ProbDesc {
   double hmc_eps;        // leapfrog step
   int32_t hmc_L;         // leapfrog steps per trajectory (0: no HMC)
   int32_t hmc_k;         // passes done in the current trajectory
+  // Guards.  A pass is out of range when the Gershgorin bound of its H
+  // exceeds tail_guard (tail only) or, when growth_limit > 0, when the
+  // largest pivot growth of the problem's matrices exceeds growth_limit
+  // (or is not finite).  Such a pass applies no ADAM update and advances
+  // no counter, so the caller can re-plan the problem and resume from the
+  // same step, whatever number of passes it had queued behind it.
+  double growth_limit;
+  double growth_run;     // running max of the pivot growth over passes
 };
+
+// ProbStats::guard bits
+constexpr int32_t kGuardTail = 1;     // tail's spectral bound exceeded
+constexpr int32_t kGuardGrowth = 2;   // pivot growth above growth_limit
 
 // Matsubara tail by moments.  For w > rho(H),
 //   ln|det(i w - H)| = N ln w + 1/2 sum_{m>=1} (-1)^(m+1)/m tr(H^2m) / w^2m,
@@ -61,6 +73,11 @@ struct ProbStats {
   int32_t nonfinite;
   int32_t tail_range;   // the tail's spectral bound exceeded its guard
   double kin0, kin;     // HMC: 1/2 sum p^2 before and after this pass's kick
+  double growth_run;    // largest pivot growth since the descriptor upload
+  int32_t guard;        // kGuard* bits of this pass
+  int32_t updated;      // this pass applied an ADAM update
+  int32_t adam_t;       // ADAM updates applied after this pass
+  int32_t steps_left;   // updates still to apply after this pass
 };
 
 // Number of lattice directions d in {+x,-x,+y,-y} with j = i + d (mod L).
@@ -72,6 +89,12 @@ __host__ __device__ inline int kmult(int i, int j, int L) {
   if (dy == 0) c += (dx == 1) + (dx == L - 1);
   if (dx == 0) c += (dy == 1) + (dy == L - 1);
   return c;
+}
+
+// max that keeps a NaN (fmax drops it): guards and absmax read a NaN as
+// out of range.
+__host__ __device__ inline double max_nan(double a, double b) {
+  return (a != a || b != b) ? a + b : (a > b ? a : b);
 }
 
 __host__ __device__ inline int stagger_sign(int i, int L) {

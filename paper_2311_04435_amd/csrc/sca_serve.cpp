@@ -64,8 +64,8 @@ struct Request {
   double* v = nullptr;
   int Me = 0;              // frequencies factorised (tail: < n_max)
   double tail_guard = 0.0;
-  int passes_total = 0;   // ADAM passes + the final evaluation (if any)
-  int passes_enq = 0;     // passes enqueued so far
+  int applied = 0;        // ADAM updates applied (device count, last chunk)
+  double gmax = 0.0;      // largest pivot growth seen
   Group* group = nullptr;
   bool done = false;
   double t_submit = 0.0, t_done = 0.0;
@@ -237,9 +237,8 @@ sca_status launch(sca_server* s, Group* g) {
       P.m = r->m; P.v = r->v; P.phi_out = r->phi;
       P.lr = r->o.lr; P.beta1 = r->o.beta1; P.beta2 = r->o.beta2;
       P.eps = r->o.eps;
-      const int applied = std::min(r->passes_enq, r->o.n_steps);
-      P.adam_t = r->o.t0 + applied;
-      P.steps_left = r->o.n_steps - applied;
+      P.adam_t = r->o.t0 + r->applied;
+      P.steps_left = r->o.n_steps - r->applied;
       P.Me = r->Me;
       P.tail_guard = r->tail_guard;
       P.mat_begin = mb;
@@ -254,8 +253,13 @@ sca_status launch(sca_server* s, Group* g) {
                                        g->st));
     g->dirty = false;
   }
+  // passes each member still needs if no guard holds one back; a chunk
+  // never runs a member past its last one
   int left = kMaxChunk;
-  for (const Request* r : g->mem) left = std::min(left, r->passes_total - r->passes_enq);
+  for (const Request* r : g->mem) {
+    const bool fe = !(r->o.flags & SCA_ADAM_NO_FINAL_EVAL);
+    left = std::min(left, std::max(1, r->o.n_steps - r->applied + (fe ? 1 : 0)));
+  }
   int K = 1;
   if (g->pass_ms > 0.0)
     K = std::max(1, std::min(left, (int)(kChunkTargetMs / g->pass_ms)));
@@ -264,15 +268,19 @@ sca_status launch(sca_server* s, Group* g) {
   SCA_HIP_TRY(hipMemcpyAsync(g->pin_stats, g->c.stats, sizeof(ProbStats) * n,
                              hipMemcpyDeviceToHost, g->st));
   SCA_HIP_TRY(hipEventRecord(g->ev, g->st));
-  for (Request* r : g->mem) r->passes_enq += K;
   g->chunk = K;
   g->inflight = true;
   g->t_launch = s->now();
   return SCA_OK;
 }
 
-// A finished chunk: members that reached their last pass retire with the
-// statistics of that pass.
+// A finished chunk.  The device counters say how many updates each member
+// has applied (a pass whose tail guard fired applied none), so the switch
+// of a tail member to every frequency happens at the pass where its guard
+// fired, whatever the chunk length and whoever shares the group.  Members
+// that reached their last pass retire with the statistics of that pass:
+// the evaluation at the returned phi, or (SCA_ADAM_NO_FINAL_EVAL) the pass
+// that applied the last update.
 void complete(sca_server* s, Group* g) {
   const double t = s->now();
   const double ms = 1e3 * (t - g->t_launch) / g->chunk;
@@ -282,25 +290,31 @@ void complete(sca_server* s, Group* g) {
   for (size_t k = 0; k < g->mem.size(); ++k) {
     Request* r = g->mem[k];
     const ProbStats& S = g->pin_stats[k];
-    if (S.tail_range && r->Me < r->p.n_max) {
+    r->applied = S.adam_t - r->o.t0;
+    r->gmax = max_nan(r->gmax, S.growth_run);
+    const bool fe = !(r->o.flags & SCA_ADAM_NO_FINAL_EVAL);
+    const bool finished =
+        S.nonfinite ||
+        (fe ? (r->applied == r->o.n_steps && !S.updated && S.guard == 0)
+            : (r->applied == r->o.n_steps && (S.updated || S.guard == 0)));
+    if (!finished && (S.guard & kGuardTail) && r->Me < r->p.n_max) {
       // the spectral bound left the tail's range: the following passes
-      // factorise every frequency
+      // factorise every frequency, from the step the guard held back
       r->res.flags |= SCA_FLAG_TAIL_RANGE;
       r->Me = r->p.n_max;
       r->tail_guard = 0.0;
       g->dirty = true;
     }
-    if (r->passes_enq < r->passes_total) { keep.push_back(r); continue; }
+    if (!finished) { keep.push_back(r); continue; }
     r->res.omega = S.omega;
     r->res.omega_tilde = S.omega_tilde;
     r->res.af_order = S.af_order;
     r->res.max_abs_grad = S.max_abs_grad;
-    r->res.max_pivot_growth = S.pivot_growth;
-    r->res.steps_done = r->o.n_steps;
+    r->res.max_pivot_growth = r->gmax;
+    r->res.steps_done = r->applied;
     r->res.flags &= SCA_FLAG_TAIL_RANGE;
-    if (S.tail_range) r->res.flags |= SCA_FLAG_TAIL_RANGE;
     if (S.nonfinite) r->res.flags |= SCA_FLAG_NONFINITE;
-    if ((route_of(&r->p) & kModeFp32) && !(S.pivot_growth <= 1e3))
+    if ((route_of(&r->p) & kModeFp32) && !(r->gmax <= 1e3))
       r->res.flags |= SCA_FLAG_PIVOT_GROWTH;
     r->done = true;
     r->t_done = t;
@@ -424,8 +438,6 @@ sca_status sca_server_submit(sca_server* s, const sca_params* p,
   r->p = *p;
   r->o = *o;
   r->phi = phi; r->m = m; r->v = v;
-  const bool final_eval = !(o->flags & SCA_ADAM_NO_FINAL_EVAL);
-  r->passes_total = std::max(1, o->n_steps + (final_eval ? 1 : 0));
   r->t_submit = s->now();
   *ticket = r->id;
   s->queue.push_back(r.get());

@@ -125,3 +125,39 @@ def test_blocked_dos(sca):
     e = rel_inf(rho, ref)
     print(f"DOS 10x10 err {e:.2e}")
     assert e < 1e-10
+
+
+@pytest.mark.parametrize("name", ["hubbard_20x20_T0.1", "hubbard_20x20_T0.6"])
+def test_lu_c2_trajectory_2000_steps(sca, name):
+    """The headline route (pivoted LU, FP64) over the 20x20 runs of 2000
+    ADAM steps against the oracle's trajectory stored by
+    tests/golden/make_c2_trajectory.py: phi after 200 and 2000 steps, |phi|,
+    Omega~ and the DOS of the final phi."""
+    import json
+    import os
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "c2_trajectory_20x20.json")
+    with open(path) as f:
+        gold = json.load(f)[name]
+    wl = synth.WORKLOADS[name]
+    p = sca.Params.from_dict(wl["params"])
+    phi0 = cuda(synth.make_phi0(20, wl["phi0"]))
+    ctx = sca.default_context()
+    phi = phi0.clone()
+    m, v = torch.zeros_like(phi), torch.zeros_like(phi)
+    ctx.adam_solve(p, phi, m, v, 200, final_eval=False)
+    ref200 = np.array(gold["phi200"])
+    e200 = np.max(np.abs(phi.cpu().numpy() - ref200)) / np.max(np.abs(ref200))
+    res = ctx.adam_solve(p, phi, m, v, 1800, t0=200)
+    ref = np.array(gold["phi2000"])
+    e = np.max(np.abs(phi.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    e_af = abs(res["af_order"] - gold["af_order"]) / max(gold["af_order"], 1e-12)
+    e_om = abs(res["omega_tilde"] - gold["omega_tilde"]) / abs(gold["omega_tilde"])
+    rho = sca.dos(p, phi, cuda(gold["dos_w"]), gold["dos_eta"]).cpu().numpy()
+    e_dos = rel_inf(rho, np.array(gold["dos"]))
+    print(f"{name} LU 2000 steps: phi@200 {e200:.2e}  phi@2000 {e:.2e}  "
+          f"|phi| {res['af_order']:.6f} ({e_af:.1e})  Omega~ {e_om:.1e}  "
+          f"DOS {e_dos:.1e}")
+    assert e200 < 1e-10 and e < 1e-10 and e_af < 1e-10
+    assert e_om < 1e-10 and e_dos < 1e-10
