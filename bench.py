@@ -94,8 +94,8 @@ def kernel_work(kind: str, N: int, B: int):
         return B * 16.0 / 3.0 * n3, "flop", "mfma"
     if kind == "wvgemm":      # X = W V, upper x unit lower: (8/3) N^3
         return B * 8.0 / 3.0 * n3, "flop", "mfma"
-    if kind == "refine":      # reads X and the W, V triangles once (FP32)
-        return B * 16.0 * N * N, "byte", "hbm"
+    if kind == "refine":      # reads X (complex64 N x N) once
+        return B * 8.0 * N * N, "byte", "hbm"
     if kind == "diagdot":     # reads the W and V triangles once
         return B * 16.0 * N * N, "byte", "hbm"
     if kind == "symdiag":     # reads the L^-T triangle once

@@ -62,12 +62,14 @@ hipError_t blocked_lu_f32(const BlockedPlan& p, const MatDesc* descs,
 hipError_t blocked_trtri_f32(const BlockedPlan& p, int B, float* F,
                              const int* perm, const float* tri,
                              hipStream_t st);
-// X = fl32(W V) for every matrix (Np a multiple of 64).
-hipError_t launch_wv_gemm(int B, int Np, const float* F, const int* perm,
-                          float* X, hipStream_t st);
-// FP64 Newton diagonal -> dg[b][N][2] and refined ln|det| -> lad[b];
-// ldpart: B * refine_blocks(Np) doubles of scratch.
-int refine_blocks(int Np);
+// X = fl32(W V) for every matrix (Np a multiple of 16), and the tiles'
+// shares of Re tr(A W V P) into ldpart (B * refine_parts(Np) doubles).
+hipError_t launch_wv_gemm(int B, int N, int Np, int L, const MatDesc* descs,
+                          const double* hbuf, const float* F, const int* perm,
+                          float* X, double* ldpart, hipStream_t st);
+// FP64 Newton diagonal -> dg[b][N][2] and refined ln|det| -> lad[b] (after
+// launch_wv_gemm on the same ldpart).
+int refine_parts(int Np);
 hipError_t launch_refine(int B, int N, int Np, int L, const MatDesc* descs,
                          const double* hbuf, const float* F, const int* perm,
                          const float* X, double* dg, double* ldpart,

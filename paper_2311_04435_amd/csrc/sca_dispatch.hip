@@ -37,7 +37,7 @@ namespace {
 
 size_t refine_extra_bytes(const BlockedPlan& p, int B) {
   return align256(sizeof(float) * 2 * (size_t)B * p.Np * p.Np)        // X
-       + align256(sizeof(double) * (size_t)B * refine_blocks(p.Np));  // parts
+       + align256(sizeof(double) * (size_t)B * refine_parts(p.Np));  // parts
 }
 
 size_t sym_extra_bytes(const BlockedPlan& p, int B) {
@@ -91,7 +91,9 @@ hipError_t fp32r_batch(const BlockedPlan& p, const MatDesc* descs,
   hipError_t e = blocked_lu_f32(p, descs, hbuf, B, N, L, bb.F, bb.perm,
                                 bb.tri, lad, growth, st);
   if (e == hipSuccess) e = blocked_trtri_f32(p, B, bb.F, bb.perm, bb.tri, st);
-  if (e == hipSuccess) e = launch_wv_gemm(B, p.Np, bb.F, bb.perm, X, st);
+  if (e == hipSuccess)
+    e = launch_wv_gemm(B, N, p.Np, L, descs, hbuf, bb.F, bb.perm, X, parts,
+                       st);
   if (e == hipSuccess)
     e = launch_refine(B, N, p.Np, L, descs, hbuf, bb.F, bb.perm, X, dg,
                       parts, lad, st);

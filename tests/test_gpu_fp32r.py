@@ -7,9 +7,11 @@ route S (spectrum of H_s, pinned to route D on the CPU) above it.
 The stated bar of the refined-FP32 route is 1e-6 relative on every result.
 The Newton step squares the FP32 residual and the log-determinant identity
 is exact up to the second-order term, so the route reaches far better; the
-asserts hold it to what it reaches, with a margin of 10-30x: per-matrix
-ln|det| 1e-11 (of max(1, |ln|det||)), diag(A^-1) 1e-8, Omega~ 1e-11, the
-gradient, an ADAM trajectory and the DOS 1e-10.
+asserts hold it to what it reaches, with a margin: per-matrix ln|det| 1e-11
+(of max(1, |ln|det||); reached <= 4e-13), diag(A^-1) 3e-8 (reached 8.4e-9
+at 48x48 on the shift -2.5 + 0.02i, whose |A^-1| is large: the one-sided
+Newton diagonal 2 Z_ii - c_i^T A c_i leaves -(R^T A^-1 R)_ii), Omega~ 1e-11,
+the gradient, an ADAM trajectory and the DOS 1e-10.
 """
 import numpy as np
 import pytest
@@ -21,7 +23,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-6          # stated bar of the route
 TOL_LAD = 1e-11     # reached (see the module docstring)
-TOL_DIAG = 1e-8
+TOL_DIAG = 3e-8
 TOL_OMEGA = 1e-11
 TOL_GRAD = 1e-10
 
