@@ -7,12 +7,14 @@ dropping the charge channel and taking a static Hubbard-Stratonovich field
 
     H_s(phi) = -t K + (Delta/2) S - s diag(phi)
 
-(the field normalisation and the Delta/2 amplitude follow the readings listed
-in the design notes).  Matsubara frequencies w_n = (2n+1) pi T (text after
-Eq. (7)).
+(phi couples as -s phi_i with the potential sum phi_i^2 / U, the paper's
+Eq. (5) form with phi rescaled by 1/2, and the ionic potential is +-Delta/2,
+i.e. Delta here is twice the paper's).  Matsubara frequencies
+w_n = (2n+1) pi T (text after Eq. (7)).
 
-Pins: the Bloch closed form (tests/test_oracle_closed.py) checks K, S and the
-sign of the field term; Leibniz brute force checks the 2x2 lattice.
+Pins (tests/test_oracle_pins.py): the Bloch spectrum of K and the staggered
+closed form check K, S and the sign of the field term; the Leibniz brute
+force checks the 2x2 lattice.
 """
 from __future__ import annotations
 

@@ -46,10 +46,21 @@ constexpr int kMaxChunk = 64;
 // problems as keep one pass near kPassFlops of factorisation work (about
 // 2 ms at the rate the FP64 kernels reach on these sizes), at least one.
 constexpr double kPassFlops = 3e10;
+// The spectral route factorises nothing: a pass is one Householder
+// reduction per spin (N dependent launches shared by every member) whose
+// traffic, about 2 x 16 N^3 / 3 bytes per problem, bounds it once the
+// launches are full; a group takes as many problems as keep that near
+// kPassBytes.
+constexpr double kPassBytes = 5e10;
 
-int group_cap(int N, int M, int max_batch) {
-  const double per_problem = 2.0 * M * (16.0 / 3.0) * (double)N * N * N;
-  const double cap = std::floor(kPassFlops / per_problem);
+int group_cap(int N, int M, int mode, int max_batch) {
+  double cap;
+  if (mode == kModeEig) {
+    cap = std::floor(kPassBytes / (2.0 * 16.0 / 3.0 * (double)N * N * N));
+  } else {
+    const double per_problem = 2.0 * M * (16.0 / 3.0) * (double)N * N * N;
+    cap = std::floor(kPassFlops / per_problem);
+  }
   return (int)std::max(1.0, std::min((double)max_batch, cap));
 }
 
@@ -165,7 +176,7 @@ sca_status new_group(sca_server* s, const Request* r, Group** out) {
   auto fits = [&](int cap) {
     return s->used + group_bytes(N, M, prec, cap) <= s->budget;
   };
-  int cap = group_cap(N, M, s->max_batch);
+  int cap = group_cap(N, M, prec, s->max_batch);
   if (!fits(cap)) make_room(s, group_bytes(N, M, prec, cap));
   while (cap > 1 && !fits(cap)) cap /= 2;
   if (!fits(cap)) return SCA_OK;   // wait until a group frees its memory

@@ -112,11 +112,14 @@ class Server:
         return out
 
 
-def run_stream(server: Server, requests, arrivals, wait_s: float = 0.0005):
+def run_stream(server: Server, requests, arrivals, wait_s: float = 0.0005,
+               on_done=None):
     """Submit request k at server time arrivals[k] (seconds from now) and run
     until all finish.  requests: list of dict(params=Params, phi0=tensor,
     n_steps=int, **adam kwargs).  Returns (results, latencies, makespan):
-    results[k] the poll result, latencies[k] = finish - arrival."""
+    results[k] the poll result, latencies[k] = finish - arrival.  on_done,
+    if given, is called with the number of finished requests each time one
+    finishes."""
     order = np.argsort(arrivals, kind="stable")
     base = server.clock()
     arr = base + np.asarray(arrivals, dtype=np.float64)
@@ -146,6 +149,8 @@ def run_stream(server: Server, requests, arrivals, wait_s: float = 0.0005):
                 results[k] = out
                 lat[k] = out[4] - arr[k]
                 pending.discard(t)
+                if on_done is not None:
+                    on_done(sum(r is not None for r in results))
         if not pending and nxt < len(order):
             time.sleep(max(0.0, min(0.001, arr[order[nxt]] - server.clock())))
     makespan = server.clock() - base
