@@ -274,6 +274,27 @@ SCA_API sca_status sca_shifted_terms(sca_ctx* ctx, const sca_params* p,
                              const double* phi, const double* z, int32_t n_z,
                              double* logabsdet, double* diag);
 
+/* sca_grad without any allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as sca_grad, but every
+ * intermediate lives in a fixed scratch array of 16 MiB compiled into the
+ * library: one per device, held from the library's load until the process
+ * ends (sca_create takes its address).  Nothing is allocated on the device
+ * or the host: descriptors go up as kernel arguments and the statistics come
+ * back through the context's stream.  A problem whose workspace exceeds the
+ * scratch (sca_footprint_bytes gives it, plus 256 bytes) is refused with
+ * SCA_ENOMEM before any device work (with SCA_TAIL_MOMENTS, after max|phi|
+ * is read for the split).  That admits the fused path up to n_max = 7807 at
+ * L = 8 (27568 at L = 4), small blocked lattices (L = 10 up to n_max = 21 in
+ * FP64, 25 in refined FP32) and the spectral route up to L = 16 (n_max =
+ * 1211).  Every call on one device shares that device's
+ * scratch and leaves its last contents there (nothing in it needs to start
+ * at zero): calls that overlap on one device, from any context or stream,
+ * race and must be serialised by the caller. */
+SCA_API sca_status sca_grad_noalloc(sca_ctx* ctx, const sca_params* p,
+                                    const double* phi, double* grad,
+                                    double* omega2);
+
 /* Differentiable split of sca_grad (a custom autograd backward of Eq. (7),
  * in place of the automatic differentiation of the determinant the paper
  * uses in Sec. III): the

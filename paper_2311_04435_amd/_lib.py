@@ -31,6 +31,7 @@ KERNEL_CLASSES = ("small", "lu", "trtri", "diagdot", "reduce", "setup",
 EXPORTS = ("sca_create", "sca_destroy", "sca_footprint_bytes", "sca_potential",
            "sca_grad", "sca_adam_solve", "sca_hmc", "sca_dos",
            "sca_shifted_terms", "sca_tail_split", "sca_set_option",
+           "sca_grad_noalloc",
            "sca_factor_bytes", "sca_factorize", "sca_grad_from_factors",
            "sca_profile", "sca_profile_read", "sca_server_create",
            "sca_server_destroy", "sca_server_clock", "sca_server_submit",
@@ -85,6 +86,7 @@ def _load():
         "sca_footprint_bytes": (C.c_size_t, [P]),
         "sca_potential": (i32, [vp, P, dp, dp]),
         "sca_grad": (i32, [vp, P, dp, dp, dp]),
+        "sca_grad_noalloc": (i32, [vp, P, dp, dp, dp]),
         "sca_adam_solve": (i32, [vp, P, O, dp, dp, dp, R]),
         "sca_hmc": (i32, [vp, P, C.POINTER(HmcOpts), dp, dp,
                           C.POINTER(C.c_double), C.POINTER(i32),

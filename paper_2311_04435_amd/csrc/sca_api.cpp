@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,8 +54,49 @@ struct sca_ctx {
   size_t pinned_bytes = 0;
   double* dscalar = nullptr;   // one device double (tail planning)
   double growth_limit = 1e3;   // SCA_OPT_FP32_GROWTH_LIMIT
+  void* scratch = nullptr;     // this device's fixed scratch (sca_grad_noalloc)
   sca::Profiler prof;
 };
+
+// ---------------------------------------------- fixed scratch (no-alloc) --
+// sca_grad_noalloc works in this array instead of the context's workspace:
+// one copy per device, allocated by the code-object loader with the library
+// and held until the process ends.  Host code never uses the array's name as
+// an address: sca_create takes each device's address once, with that device
+// current (hipGetSymbolAddress), and passes that pointer on.
+namespace {
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// The device's scratch address; `device` must be the current device.
+sca_status scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices)
+    return sca::fail(SCA_EDEVICE, "device %d beyond the %d this library "
+                     "tracks", device, kMaxDevices);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return sca::fail(SCA_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s",
+                       hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return SCA_OK;
+}
+
+// Writes one problem descriptor to device memory from the kernel argument
+// (no staging buffer on the host).
+__global__ void store_desc_kernel(sca::ProbDesc* dst, sca::ProbDesc P) {
+  *dst = P;
+}
+}  // namespace
 
 namespace sca {
 
@@ -412,6 +454,75 @@ sca_status eval_single(sca_ctx* ctx, const sca_params* p, const double* phi,
   return SCA_OK;
 }
 
+// eval_single in the device's fixed scratch: nothing is allocated on the
+// device or the host (descriptors go up as kernel arguments, statistics come
+// back into the caller's stack through the stream).  Layout of the scratch:
+// one double for the tail planning at 0, the batch's carve from 256.
+sca_status eval_single_noalloc(sca_ctx* ctx, const sca_params* p,
+                               const double* phi, double* grad,
+                               double* omega2) {
+  const int N = p->L * p->L;
+  const int mode = route_of(p);
+  hipStream_t st = ctx->stream;
+  char* base = static_cast<char*>(ctx->scratch);
+  ProbDesc P = make_prob(p, phi, grad);
+  if (p->tail == SCA_TAIL_MOMENTS) {
+    double pmax = 0.0, omax = 0.0;
+    double* dsc = reinterpret_cast<double*>(base);
+    HIP_TRY(launch_absmax(phi, N, dsc, st));
+    HIP_TRY(hipMemcpyAsync(&pmax, dsc, sizeof pmax, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (p->onsite) {
+      HIP_TRY(launch_absmax(p->onsite, N, dsc, st));
+      HIP_TRY(hipMemcpyAsync(&omax, dsc, sizeof omax, hipMemcpyDeviceToHost,
+                             st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (!std::isfinite(pmax) || !std::isfinite(omax))
+      return fail(SCA_ENUMERIC, "phi or onsite is not finite");
+    tail_split(p, pmax, omax, P);
+  }
+  P.growth_limit = device_growth_limit(ctx, N, mode);
+  const int B = 2 * P.Me;
+  const size_t fb = factor_workspace_bytes(N, B, mode);
+  const Carve c0 = carve(nullptr, 1, N, B, mode, true, true, fb);
+  if (256 + c0.total > kNoAllocBytes)
+    return fail(SCA_ENOMEM, "L=%d, n_max=%d needs %zu bytes of scratch; the "
+                "fixed scratch of sca_grad_noalloc holds %zu", p->L,
+                p->n_max, 256 + c0.total, kNoAllocBytes);
+  Carve c = carve(base + 256, 1, N, B, mode, true, true, fb);
+  c.tail_on = P.Me < P.M;
+  hipLaunchKernelGGL(store_desc_kernel, dim3(1), dim3(1), 0, st, c.probs, P);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_matsubara_descs(c.probs, 1, B, c.descs, st));
+  HIP_TRY(enqueue_pass(c, 1, p->L, B, mode, false, st));
+  ProbStats S;
+  HIP_TRY(hipMemcpyAsync(&S, c.stats, sizeof S, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (S.tail_range) {
+    sca_params q = *p;
+    q.tail = SCA_TAIL_NONE;
+    return eval_single_noalloc(ctx, &q, phi, grad, omega2);
+  }
+  if (growth_exceeded(ctx, mode, S.pivot_growth)) {
+    if (!path_supported(N, mode & ~kModeFp32))
+      return fail(SCA_ENUMERIC, "FP32 pivot growth %.3g above %.3g and no "
+                  "FP64 path for N=%d", S.pivot_growth, ctx->growth_limit, N);
+    sca_params q = *p;
+    q.precision = SCA_FP64;
+    return eval_single_noalloc(ctx, &q, phi, grad, omega2);
+  }
+  if (omega2) {
+    // Omega and Omega~ lead ProbStats
+    HIP_TRY(hipMemcpyAsync(omega2, c.stats, 2 * sizeof(double),
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  if (S.nonfinite)
+    return fail(SCA_ENUMERIC, "non-finite potential or gradient");
+  return SCA_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- C ABI -----
@@ -436,10 +547,17 @@ sca_status sca_create(int device, void* hip_stream, size_t hbm_budget_bytes,
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(SCA_EDEVICE, "device %d is %s; this library is built for gfx950",
                 device, prop.gcnArchName);
+  void* scr = nullptr;
+  {
+    DeviceGuard g(device);
+    sca_status s = scratch_address(device, &scr);
+    if (s) return s;
+  }
   sca_ctx* ctx = new sca_ctx;
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->budget = hbm_budget_bytes;
+  ctx->scratch = scr;
   *out = ctx;
   return SCA_OK;
 }
@@ -480,6 +598,19 @@ sca_status sca_grad(sca_ctx* ctx, const sca_params* p, const double* phi,
   if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
   if ((s = check_dev_ptr(ctx, omega2, "omega2", true))) return s;
   return eval_single(ctx, p, phi, grad, omega2, nullptr);
+}
+
+sca_status sca_grad_noalloc(sca_ctx* ctx, const sca_params* p,
+                            const double* phi, double* grad, double* omega2) {
+  sca_status s = begin_call(ctx, p);
+  if (s) return s;
+  if (!ctx->scratch)
+    return fail(SCA_EDEVICE, "the context has no fixed scratch");
+  DeviceGuard g(ctx, ctx->device);
+  if ((s = check_dev_ptr(ctx, phi, "phi"))) return s;
+  if ((s = check_dev_ptr(ctx, grad, "grad"))) return s;
+  if ((s = check_dev_ptr(ctx, omega2, "omega2", true))) return s;
+  return eval_single_noalloc(ctx, p, phi, grad, omega2);
 }
 
 sca_status sca_adam_solve(sca_ctx* ctx, const sca_params* p,
