@@ -138,49 +138,68 @@ def hmc_line(sca, name, n_traj=4, n_leap=10, eps=0.02, factor="ldlt",
             "mean_abs_dH": float(abs(h1 - h0).mean())}
 
 
-def cpu_baseline(wl, budget_s: float):
-    """The FP64 oracle on this host: route D (the same pivoted LU per
-    matrix) on a sample of matrices, and route S (eigendecomposition)."""
+def cpu_baseline(budget_s: float):
+    """The FP64 oracle on this host's cores, over whole ADAM steps only (no
+    extrapolation): route D (the method's definition: a pivoted complex LU
+    and inverse per Matsubara matrix, NumPy) on one whole step of the 20x20
+    workload (1024 matrices of 400 x 400) and on whole steps of the 4x4
+    workload; route S (one eigendecomposition per spin, algorithmically
+    ~n_max times cheaper) on whole 20x20 steps for about budget_s."""
     import numpy as np
     import oracle
+    from oracle.adam import AdamState, adam_step
     import synth
     try:
         from threadpoolctl import threadpool_info
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
+        threads = 1
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except Exception:
+        avail = nproc
+
+    def route_d_steps(name, min_s, max_steps):
+        wl = synth.WORKLOADS[name]
+        p = dict(wl["params"])
+        hy = wl["adam"]
+        x = synth.make_phi0(p["L"], wl["phi0"])
+        st = AdamState.zeros(x.size)
+        t0 = time.perf_counter()
+        steps = 0
+        while steps < max_steps and (steps == 0 or
+                                     time.perf_counter() - t0 < min_s):
+            g = oracle.grad_d(p, x)
+            x = adam_step(x, g, st, hy["lr"], hy["beta1"], hy["beta2"], hy["eps"])
+            steps += 1
+        return steps, time.perf_counter() - t0
+
+    n20, t20 = route_d_steps("hubbard_20x20_T0.1", 0.0, 1)
+    n4, t4 = route_d_steps("hubbard_4x4", 3.0, 1000)
+    wl = synth.WORKLOADS["hubbard_20x20_T0.1"]
     p = dict(wl["params"])
-    L, M = p["L"], p["n_max"]
-    B = 2 * M
-    phi = synth.make_phi0(L, wl["phi0"])
-    w = oracle.matsubara(p["T"], M)
-    # route D: LU + inverse of matrices spread over the frequency range
+    phi = synth.make_phi0(p["L"], wl["phi0"])
     t0 = time.perf_counter()
-    done = 0
-    idx = np.linspace(0, M - 1, 64).astype(int)
-    for k in range(64):
-        spin = 1 if k % 2 == 0 else -1
-        oracle.shifted_terms(p, phi, [1j * w[idx[k]]], spin)
-        done += 1
-        if time.perf_counter() - t0 > 0.5 * budget_s:
-            break
-    per_mat = (time.perf_counter() - t0) / done
-    route_d = 1.0 / (per_mat * B)
-    # route S: whole ADAM steps
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < 0.5 * budget_s:
+    ns = 0
+    while ns == 0 or time.perf_counter() - t0 < budget_s:
         oracle.adam_solve(p, phi, 1)
-        steps += 1
-    route_s = steps / (time.perf_counter() - t0)
-    return {"value": route_d, "unit": "steps/s", "cores": int(threads),
+        ns += 1
+    ts = time.perf_counter() - t0
+    return {"value": n20 / t20, "unit": "steps/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": (f"route D (pivoted complex LU + inverse per matrix, "
-                       f"NumPy FP64): {done} of the {B} matrices of one step, "
-                       f"{per_mat:.3f} s each, scaled to a full step; route S "
-                       f"(eigendecomposition, algorithmically ~{M}x cheaper): "
-                       f"{steps} whole steps"),
-            "route_s_steps_per_s": route_s}
+            "sample": (f"route D (pivoted complex LU + inverse of each of the "
+                       f"1024 Matsubara matrices of 400 x 400, NumPy FP64, "
+                       f"then the ADAM update): {n20} whole step of the 20x20 "
+                       f"workload in {t20:.1f} s"),
+            "nproc": nproc, "cpus_available": avail, "blas_threads": int(threads),
+            "route_d_4x4": {"steps": n4, "seconds": t4,
+                            "steps_per_s": n4 / t4},
+            "route_s_20x20": {"steps": ns, "seconds": ts,
+                              "steps_per_s": ns / ts,
+                              "note": "eigendecomposition of H per spin and "
+                                      "closed Matsubara sums: O(N^3) per step "
+                                      "instead of O(n_max N^3)"}}
 
 
 def workload_rate(sca, name, prec, steps, warmup, factor="lu", tail=False):
@@ -280,13 +299,16 @@ def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0,
         r = next(q for q in reqs if q["params"].L == L)
         sca.adam_solve(r["params"], r["phi0"], 1)
     service, alone = [], []
-    for r in reqs:
+    for k, r in enumerate(reqs):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = sca.adam_solve(r["params"], r["phi0"], r["n_steps"])
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t0)
         alone.append(out[0])
+        if (k + 1) % 32 == 0:
+            print(f"bench: serving, one at a time {k + 1}/{len(reqs)} "
+                  f"({sum(service):.1f} s)", file=sys.stderr, flush=True)
     service = np.array(service)
     print(f"bench: serving, one-at-a-time pass {service.sum():.1f} s",
           file=sys.stderr, flush=True)
@@ -298,11 +320,18 @@ def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0,
         warm = [srv.submit(r["params"], r["phi0"], 1)
                 for r in {q["params"].L: q for q in reqs}.values()]
         srv.drain(warm)
-        results, lat, span = run_stream(srv, reqs, arrivals)
+        def done(n):
+            if n % 32 == 0:
+                print(f"bench: serving, served {n}/{len(reqs)}",
+                      file=sys.stderr, flush=True)
+        results, lat, span = run_stream(srv, reqs, arrivals, on_done=done)
     print(f"bench: serving, served pass {span:.1f} s", file=sys.stderr,
           flush=True)
     same = all(torch.equal(results[k][0], alone[k]) for k in range(len(reqs)))
     del ctx
+    by_L = {}
+    for r, t in zip(reqs, service):
+        by_L.setdefault(r["params"].L, []).append(t)
     return {"workload": (f"{n_req} requests, L in {sorted(set(Ls))}, "
                          f"n_max={n_max}, {steps} ADAM steps each, FP64 "
                          f"({ {'lu': 'pivoted LU', 'ldlt': 'L D L^T', 'eigh': 'spectral'}[factor] }"
@@ -312,7 +341,19 @@ def serving(sca, n_req, steps, n_max, Ls, max_batch, load=1.5, seed=0,
             "max_batch": max_batch,
             "served": latency_summary(lat, span),
             "fifo_one_at_a_time": latency_summary(fifo_lat, fifo_span),
-            "alone_vs_mix_bitwise": bool(same)}
+            "alone_vs_mix_bitwise": bool(same),
+            "service_s_by_L": {str(k): {"requests": len(v),
+                                        "mean_s": float(np.mean(v))}
+                               for k, v in sorted(by_L.items())}}
+
+
+def c1_line(sca, steps=500, warmup=20):
+    """The 4x4 workload (512 matrices of 16 x 16 per step, fused small
+    kernel): microseconds per ADAM step; launch- and latency-bound, so no
+    roofline fraction is claimed."""
+    out = workload_rate(sca, "hubbard_4x4", "fp64", steps, warmup)
+    out["us_per_step"] = 1e3 * out["ms_per_step"]
+    return out
 
 
 def main():
@@ -324,9 +365,12 @@ def main():
     ap.add_argument("--precision", default=None, help="fp64 | fp32r")
     ap.add_argument("--factor", default="lu",
                     help="lu (pivoted, default) | ldlt (symmetric, unpivoted)")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="route S part of the CPU baseline (route D always "
+                         "times one whole 20x20 step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-l32", action="store_true")
+    ap.add_argument("--no-l32", action="store_true",
+                    help="skip the 32x32 and 48x48 lines")
     ap.add_argument("--no-tail", action="store_true",
                     help="skip the Matsubara-tail lines")
     ap.add_argument("--no-spectral", action="store_true",
@@ -335,13 +379,17 @@ def main():
                     help="skip the Hybrid Monte Carlo line")
     ap.add_argument("--no-symmetric", action="store_true",
                     help="skip the symmetric-route line")
-    ap.add_argument("--serving-requests", type=int, default=32,
+    ap.add_argument("--serving-requests", type=int, default=256,
                     help="0 skips the serving measurement")
     ap.add_argument("--serving-steps", type=int, default=200)
     ap.add_argument("--serving-nmax", type=int, default=256)
-    ap.add_argument("--serving-L", default="8,12,16,20")
+    ap.add_argument("--serving-L", default="8,12,16,20,24,32")
     ap.add_argument("--serving-batch", type=int, default=16)
-    ap.add_argument("--serving-factor", default="lu", help="lu | ldlt")
+    ap.add_argument("--serving-factor", default="eigh",
+                    help="lu | ldlt | eigh (every route computes the same "
+                         "sums; eigh is the fastest on this stream)")
+    ap.add_argument("--serving-tail", action="store_true",
+                    help="serve with the Matsubara tail by moments")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), "
                          "the reference for the HBM byte counters")
@@ -352,7 +400,6 @@ def main():
               "with one all-reduce of the gradient per step)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.calibrate_copy:
@@ -369,6 +416,9 @@ def main():
 
     import paper_2311_04435_amd as sca
     import synth
+
+    def note(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
 
     wl = synth.WORKLOADS[args.workload]
     prec = args.precision or wl.get("precision", "fp64")
@@ -396,6 +446,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     steps_per_s = args.steps / dt
+    note(f"{args.workload} {prec} {args.factor}: {steps_per_s:.2f} steps/s")
 
     # second pass of the same steps with per-kernel HIP events
     phi2, m2, v2 = phi0.clone(), torch.zeros_like(phi0), torch.zeros_like(phi0)
@@ -451,13 +502,26 @@ def main():
                   "max_abs_grad": res["max_abs_grad"],
                   "max_pivot_growth": res["max_pivot_growth"]},
     }
+    if args.factor == "lu" and prec == "fp64":
+        # the refined-FP32 route on the same workload, and on 32x32
+        out["fp32r"] = [route_line(sca, args.workload, "fp32r", "lu",
+                                   args.steps, args.warmup)]
+        out["fp32r_vs_fp64"] = out["fp32r"][0]["steps_per_s"] / steps_per_s
+        note(f"fp32r {out['fp32r'][0]['steps_per_s']:.2f} steps/s")
+        out["c1"] = c1_line(sca)
+        note(f"4x4: {out['c1']['us_per_step']:.1f} us/step")
     if not args.no_l32:
-        out["l32"] = [workload_rate(sca, "ionic_32x32_U4", "fp32r", 5, 1),
-                      workload_rate(sca, "ionic_32x32_U4", "fp64", 3, 1),
-                      workload_rate(sca, "ionic_32x32_U4", "fp64", 5, 1,
-                                    "ldlt"),
-                      workload_rate(sca, "ionic_32x32_U4", "fp64", 20, 2,
-                                    "eigh")]
+        l32 = [route_line(sca, "ionic_32x32_U4", "fp32r", "lu", 5, 1),
+               route_line(sca, "ionic_32x32_U4", "fp64", "lu", 3, 1),
+               route_line(sca, "ionic_32x32_U4", "fp64", "ldlt", 5, 1),
+               route_line(sca, "ionic_32x32_U4", "fp64", "eigh", 20, 2)]
+        out["l32"] = l32
+        note("32x32 " + ", ".join(f"{r['precision']}/{r['factor']} "
+                                  f"{r['steps_per_s']:.2f}" for r in l32))
+        out["l48"] = [route_line(sca, "ionic_48x48", "fp32r", "lu", 3, 1),
+                      route_line(sca, "ionic_48x48", "fp64", "eigh", 5, 1)]
+        note("48x48 " + ", ".join(f"{r['precision']}/{r['factor']} "
+                                  f"{r['steps_per_s']:.2f}" for r in out["l48"]))
     if args.factor == "lu" and prec == "fp64" and not args.no_symmetric:
         # the same workload on the symmetric route (unpivoted L D L^T)
         out["symmetric_ldlt"] = route_line(sca, args.workload, "fp64", "ldlt",
@@ -469,39 +533,21 @@ def main():
                        for f in ("lu", "ldlt")]
     if prec == "fp64" and not args.no_spectral:
         # one eigendecomposition per spin instead of a factorisation per
-        # frequency: the same workload, and the 48x48 ionic lattice against
-        # its factorisation route (FP32 refined)
-        out["spectral"] = [
-            route_line(sca, args.workload, "fp64", "eigh",
-                       max(args.steps, 20), args.warmup),
-            workload_rate(sca, "ionic_48x48", "fp64", 5, 1, "eigh")]
-        if not args.no_l32:
-            out["spectral"].append(workload_rate(sca, "ionic_48x48", "fp32r",
-                                                 1, 1))
+        # frequency
+        out["spectral"] = [route_line(sca, args.workload, "fp64", "eigh",
+                                      max(args.steps, 20), args.warmup)]
     if prec == "fp64" and not args.no_hmc:
         out["hmc"] = hmc_line(sca, args.workload)
+    note("route lines done")
     if args.serving_requests > 0:
         Ls = tuple(int(x) for x in args.serving_L.split(","))
         out["serving"] = serving(sca, args.serving_requests, args.serving_steps,
                                  args.serving_nmax, Ls, args.serving_batch,
-                                 factor=args.serving_factor)
-        if not args.no_tail:
-            # the same stream with the high frequencies from the moments
-            out["serving_tail"] = serving(sca, args.serving_requests,
-                                          args.serving_steps,
-                                          args.serving_nmax, Ls,
-                                          args.serving_batch,
-                                          factor=args.serving_factor,
-                                          tail=True)
-        if not args.no_spectral:
-            # the same stream on the spectral route
-            out["serving_spectral"] = serving(sca, args.serving_requests,
-                                              args.serving_steps,
-                                              args.serving_nmax, Ls,
-                                              args.serving_batch,
-                                              factor="eigh")
+                                 factor=args.serving_factor,
+                                 tail=args.serving_tail)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        note("CPU baseline (one whole 20x20 route-D step, ~1 min)")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
