@@ -69,8 +69,10 @@ size_t lu_lds_bytes(int Np, int NB, int waves, bool rp = false) {
   return b + 256;
 }
 
-template <typename T, int WAVES, int RT, int CT, bool kRP = false>
-__global__ void __launch_bounds__(WAVES * 64)
+// OCC: workgroups per CU the instance is sized for (its registers are
+// capped at 512 / (OCC * WAVES / 4) per lane).
+template <typename T, int WAVES, int RT, int CT, bool kRP = false, int OCC = 1>
+__global__ void __launch_bounds__(WAVES * 64, OCC * WAVES / 4)
 lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
           int N, int Np, int L, T* __restrict__ F,
           int* __restrict__ perm_out, T* __restrict__ tri,
@@ -838,8 +840,8 @@ size_t trtri_lds_bytes(int Np, int NB) {
   return sizeof(int) * Np + sizeof(T) * 6 * NB * (NB + 1) + 64;
 }
 
-template <typename T, int WAVES, int RT, int CT>
-__global__ void __launch_bounds__(WAVES * 64)
+template <typename T, int WAVES, int RT, int CT, int OCC = 1>
+__global__ void __launch_bounds__(WAVES * 64, OCC * WAVES / 4)
 trtri_kernel(int Np, T* __restrict__ F, const int* __restrict__ perm_g,
              const T* __restrict__ tri, const int* __restrict__ only,
              int want) {
@@ -1149,13 +1151,13 @@ diagdot_kernel(int N, int Np, const T* __restrict__ F,
 
 namespace {
 
-template <typename T, int WAVES, int RT, int CT, bool kRP = false>
+template <typename T, int WAVES, int RT, int CT, bool kRP = false, int OCC = 1>
 hipError_t run_lu(const MatDesc* descs, const double* hbuf, int B, int N,
                   int Np, int L, T* F, int* perm, T* tri, double* lad,
                   double* growth, hipStream_t st, const int* only = nullptr,
                   int want = 0) {
   const size_t lds = lu_lds_bytes<T>(Np, 16 * CT, WAVES, kRP);
-  auto kern = lu_kernel<T, WAVES, RT, CT, kRP>;
+  auto kern = lu_kernel<T, WAVES, RT, CT, kRP, OCC>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
@@ -1168,14 +1170,14 @@ hipError_t run_lu(const MatDesc* descs, const double* hbuf, int B, int N,
 }
 
 // both: W = U^-1 and V = L^-1 (grid y = 2); otherwise only W.
-template <typename T, int WAVES, int RT, int CT>
+template <typename T, int WAVES, int RT, int CT, int OCC = 1>
 hipError_t run_trtri(int B, int Np, T* F, const int* perm, const T* tri,
                      hipStream_t st, bool both = true,
                      const int* only = nullptr, int want = 0) {
   const size_t lds = trtri_lds_bytes<T>(Np, 16 * CT);
   const int cls = !both ? K_TRTRI_SYM : only ? K_FALLBACK : K_TRTRI;
   mark_begin(cls, st);
-  hipLaunchKernelGGL((trtri_kernel<T, WAVES, RT, CT>), dim3(B, both ? 2 : 1),
+  hipLaunchKernelGGL((trtri_kernel<T, WAVES, RT, CT, OCC>), dim3(B, both ? 2 : 1),
                      dim3(WAVES * 64), lds, st, Np, F, perm, tri, only, want);
   mark_end(cls, st);
   return hipGetLastError();
@@ -1200,8 +1202,10 @@ BlockedPlan blocked_plan(int N, bool fp32) {
   // accumulators.  FP64: 4 waves x 4 tiles (Np <= 256), 8 x 4 (Np <= 512)
   // with NB = 32, then NB = 16 up to Np = 1024.  FP32 (half the registers):
   // the same up to 512, NB = 32 on 8 x 8 tiles up to 1024, NB = 16 on
-  // 8 x 18 tiles up to 2304; Np is a multiple of 64 there, the tile of the
-  // W V product that follows.
+  // 8 x 18 tiles up to 2304; Np is a multiple of 32.  FP32 with
+  // 256 < Np <= 448 (cfg 4) runs the 8 x 4 LU and inverts with 4 waves x 7
+  // tiles, two workgroups per CU (4.70 against 5.06 ms at Np = 416, as
+  // measured; the LU as 4 x 7 at two per CU was slower, 8.2 against 6.0).
   BlockedPlan p{};
   p.cfg = -1;
   if (!fp32) {
@@ -1212,6 +1216,7 @@ BlockedPlan blocked_plan(int N, bool fp32) {
   } else {
     const int n32 = (N + 31) / 32 * 32;
     if (n32 <= 256) { p.cfg = 0; p.NB = 32; p.Np = n32; }
+    else if (n32 <= 448) { p.cfg = 4; p.NB = 32; p.Np = n32; }
     else if (n32 <= 512) { p.cfg = 1; p.NB = 32; p.Np = n32; }
     else if (n32 <= 1024) { p.cfg = 2; p.NB = 32; p.Np = n32; }
     else if (n32 <= 2304) { p.cfg = 3; p.NB = 16; p.Np = n32; }
@@ -1268,6 +1273,7 @@ hipError_t blocked_lu_f32(const BlockedPlan& p, const MatDesc* descs,
     case 1: return run_lu<float, 8, 4, 2, true>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     case 2: return run_lu<float, 8, 8, 2>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     case 3: return run_lu<float, 8, 18, 1>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
+    case 4: return run_lu<float, 8, 4, 2, true>(descs, hbuf, B, N, p.Np, L, F, perm, tri, lad, growth, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1280,6 +1286,7 @@ hipError_t blocked_trtri_f32(const BlockedPlan& p, int B, float* F,
     case 1: return run_trtri<float, 8, 4, 2>(B, p.Np, F, perm, tri, st);
     case 2: return run_trtri<float, 8, 8, 2>(B, p.Np, F, perm, tri, st);
     case 3: return run_trtri<float, 8, 18, 1>(B, p.Np, F, perm, tri, st);
+    case 4: return run_trtri<float, 4, 7, 2, 2>(B, p.Np, F, perm, tri, st);
     default: return hipErrorInvalidValue;
   }
 }
