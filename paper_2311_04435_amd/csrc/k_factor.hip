@@ -474,23 +474,35 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         }
       }
       __syncthreads();
-      // B: the winner over the waves and its row (all candidates loaded
-      //    first, then a branch-free selection)
-      double cmv[WAVES];
-      int cpv[WAVES];
-#pragma unroll
-      for (int v = 0; v < WAVES; ++v) { cmv[v] = S.cmag[par * WAVES + v]; cpv[v] = S.crowi[par * WAVES + v]; }
-      double bm = cmv[0];
-      int piv = cpv[0], ww = 0;
-#pragma unroll
-      for (int v = 1; v < WAVES; ++v) {
-        const bool better = (cmv[v] > bm) | ((cmv[v] == bm) & (cpv[v] < piv));
-        bm = better ? cmv[v] : bm;
-        piv = better ? cpv[v] : piv;
-        ww = better ? v : ww;
-      }
+      // B: the winner over the waves.  Lane v of every group of WAVES lanes
+      //    reads wave v's candidate (magnitude, position and pivot value, in
+      //    one round of independent loads); DPP steps inside the group then
+      //    leave the winner (largest magnitude, lowest position on ties; the
+      //    eligible positions are distinct, so it is unique) in every lane.
+      static_assert(WAVES == 4 || WAVES == 8 || WAVES == 16, "group of waves");
+      int cw = lane & (WAVES - 1);
+      double bm = S.cmag[par * WAVES + cw];
+      int piv = S.crowi[par * WAVES + cw];
+      double pvr = S.slr[(par * WAVES + cw) * 2 * NB + 2 * j];
+      double pvi = S.slr[(par * WAVES + cw) * 2 * NB + 2 * j + 1];
+      auto merge = [&](auto ctl) {
+        constexpr int C = decltype(ctl)::value;
+        const double om = dpp_d<C>(bm), orr = dpp_d<C>(pvr), oi = dpp_d<C>(pvi);
+        const int op = dpp_i<C>(piv), ow = dpp_i<C>(cw);
+        const bool better = (om > bm) | ((om == bm) & (op < piv));
+        bm = better ? om : bm;
+        piv = better ? op : piv;
+        cw = better ? ow : cw;
+        pvr = better ? orr : pvr;
+        pvi = better ? oi : pvi;
+      };
+      merge(std::integral_constant<int, 0xB1>{});   // lane pairs
+      merge(std::integral_constant<int, 0x4E>{});   // quads
+      if constexpr (WAVES >= 8) merge(std::integral_constant<int, 0x141>{});
+      if constexpr (WAVES >= 16) merge(std::integral_constant<int, 0x140>{});
+      piv = __builtin_amdgcn_readfirstlane(piv);
+      const int ww = __builtin_amdgcn_readfirstlane(cw);
       const T* prow = S.slr + (par * WAVES + ww) * 2 * NB;
-      const double pvr = prow[2 * j], pvi = prow[2 * j + 1];
       const double rden = 1.0 / (pvr * pvr + pvi * pvi);
       const T ivr = T(pvr * rden), ivi = T(-pvi * rden);
       {
