@@ -57,11 +57,12 @@ void __asan_unpoison_memory_region(void const volatile* addr, size_t size);
 #endif
 
 // x86-64 System V context switch: saves the callee-saved registers on the
-// current stack, stores the stack pointer to *save, continues on `to`.
+// current stack, stores the stack pointer to *save, continues on `to`
+// (weak: every translation unit that includes this header defines it).
 extern "C" void emu_ctx_switch(void** save, void* to);
 asm(R"(
   .text
-  .globl emu_ctx_switch
+  .weak emu_ctx_switch
   .type emu_ctx_switch, @function
 emu_ctx_switch:
   pushq %rbp

@@ -26,12 +26,25 @@ Sizes: every instance at a lattice that leaves most of its row-tile slots
 empty (the partial-tile paths).  SCA_EMU_FULL=1 in the environment adds the
 complex64 instances at N = 1600, 1936 and 2304 (minutes each, optimised
 build).
+
+The whole library (every source under csrc/, host code included, with the
+stand-in HIP runtime of tests/emu/hip/hip_runtime.h) is also built as a
+shared object and driven through its C ABI by tests/emu/lib_cases.py in
+processes with the AddressSanitizer runtime preloaded: sca_grad on every
+route (fused, blocked FP64, refined FP32, L D L^T, spectral, moment tail),
+sca_adam_solve, sca_dos, sca_hmc against the oracle; the autograd split and
+sca_grad_noalloc against sca_grad, and served requests against the same
+solves alone, bit for bit.
 """
+import concurrent.futures
+import glob
+import json
 import os
 import re
 import shutil
 import struct
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -194,3 +207,91 @@ def test_complex64_lu_large_emulated(tmp_path_factory, config, L, Np):
     _, errs = run_case(exe, tmp, config, L, Np, B=1, timeout=7200)
     t_lad, t_dg = _tol(config)
     assert errs[0][0] < t_lad and errs[0][1] < t_dg, errs
+
+
+# ---- the whole library through its C ABI -----------------------------------
+
+LIB_CASES = ["grad_small", "grad_blocked", "grad_fp32r", "grad_ldlt",
+             "grad_eigh", "grad_tail", "adam", "dos", "factors", "noalloc",
+             "server", "hmc"]
+
+
+def _asan_runtime():
+    hits = glob.glob(os.path.join(os.path.dirname(os.path.dirname(_clang())),
+                                  "lib", "clang", "*", "lib", "linux",
+                                  "libclang_rt.asan-x86_64.so"))
+    return hits[0] if hits else None
+
+
+def build_library(tmp, opt="-O0"):
+    """Every source of the library, host code included, as libsca_emu.so."""
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) +
+                  glob.glob(os.path.join(CSRC, "*.cpp")))
+    srcs.append(os.path.join(ROOT, "tests", "emu", "emu_exports.cpp"))
+    flags = [opt, "-g0", "-fPIC", "-fsanitize=address", "-shared-libasan",
+             "-fno-omit-frame-pointer", "-ftrivial-auto-var-init=pattern",
+             "-Wno-psabi", "-Wno-unknown-attributes"]
+
+    def compile_one(src):
+        cc = os.path.join(tmp, os.path.basename(src).replace(".", "_") + ".cc")
+        with open(src) as f:
+            text = f.read()
+        with open(cc, "w") as f:
+            f.write(transform(text))
+        obj = cc[:-3] + ".o"
+        r = subprocess.run([_clang(), "-std=c++17", *flags,
+                            "-I", os.path.join(ROOT, "tests", "emu"),
+                            "-I", CSRC, "-I", os.path.join(ROOT, "include"),
+                            "-isystem", "/opt/rocm/include", "-c", cc,
+                            "-o", obj], capture_output=True, text=True)
+        return obj, r
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=8) as ex:
+        built = list(ex.map(compile_one, srcs))
+    for obj, r in built:
+        assert r.returncode == 0, r.stderr[-3000:]
+    lib = os.path.join(tmp, "libsca_emu.so")
+    r = subprocess.run([_clang(), "-shared", "-fsanitize=address",
+                        "-shared-libasan", "-o", lib,
+                        *[o for o, _ in built], "-L/opt/rocm/lib",
+                        "-lrocprofiler-sdk-roctx",
+                        "-Wl,-rpath,/opt/rocm/lib"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return lib
+
+
+@pytest.fixture(scope="module")
+def lib_results(tmp_path_factory):
+    if _clang() is None or _asan_runtime() is None:
+        pytest.skip("clang++ or its AddressSanitizer runtime not available")
+    lib = build_library(str(tmp_path_factory.mktemp("emu_lib")))
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = _asan_runtime()
+    env["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1"
+    script = os.path.join(ROOT, "tests", "emu", "lib_cases.py")
+
+    def run(case):
+        r = subprocess.run([sys.executable, script, lib, case],
+                           capture_output=True, text=True, env=env,
+                           timeout=900)
+        return case, r
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=6) as ex:
+        return dict(ex.map(run, LIB_CASES))
+
+
+@pytest.mark.parametrize("case", LIB_CASES)
+def test_library_emulated(lib_results, case):
+    r = lib_results[case]
+    report = r.stdout + r.stderr
+    assert "AddressSanitizer" not in report, report[-4000:]
+    assert "EMU ERROR" not in report, report[-4000:]
+    assert r.returncode == 0, report[-4000:]
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    # FP64 routes: the 1e-10 parity bar; the refined FP32 route: 1e-6
+    tol = 1e-6 if case == "grad_fp32r" else 1e-10
+    for name, err in out["errors"].items():
+        assert err < tol, (case, name, err)
+    for name, ok in out["bitwise"].items():
+        assert ok, (case, name)
