@@ -5,11 +5,15 @@ AddressSanitizer runtime preloaded).
 
     python tests/emu/lib_cases.py <libsca_emu.so> <case>
 
-prints one JSON line {"case": ..., "errors": {...}, "bitwise": {...}} and
-exits 0, or raises.  The ctypes signatures are the product binding's own
-(paper_2311_04435_amd/_lib.py, executed with its library path replaced).
+prints one JSON line {"case": ..., "errors": {...}, "bitwise": {...},
+"digest": ...} and exits 0, or raises; the digest is a SHA-256 of every
+output the case read back.  EMU_ORDER in the environment sets the
+emulator's scheduling order (0 forward, 1 reverse, 2 random).  The ctypes
+signatures are the product binding's own (paper_2311_04435_amd/_lib.py,
+executed with its library path replaced).
 """
 import ctypes as C
+import hashlib
 import json
 import os
 import sys
@@ -42,6 +46,8 @@ def bind(path):
 
 
 S, E = bind(sys.argv[1])
+E.emu_set_order(int(os.environ.get("EMU_ORDER", "0")))
+DIGEST = hashlib.sha256()
 
 
 def dev(a, dtype=np.float64):
@@ -59,6 +65,7 @@ def zeros(n, dtype=np.float64):
 def host(p, n, dtype=np.float64):
     out = np.empty(n, dtype)
     C.memmove(out.ctypes.data, p, out.nbytes)
+    DIGEST.update(out.tobytes())
     return out
 
 
@@ -241,4 +248,5 @@ CASES = {
 if __name__ == "__main__":
     name = sys.argv[2]
     errs, bits = CASES[name]()
-    print(json.dumps({"case": name, "errors": errs, "bitwise": bits}))
+    print(json.dumps({"case": name, "errors": errs, "bitwise": bits,
+                      "digest": DIGEST.hexdigest()}))

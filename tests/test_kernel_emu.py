@@ -34,7 +34,8 @@ processes with the AddressSanitizer runtime preloaded: sca_grad on every
 route (fused, blocked FP64, refined FP32, L D L^T, spectral, moment tail),
 sca_adam_solve, sca_dos, sca_hmc against the oracle; the autograd split and
 sca_grad_noalloc against sca_grad, and served requests against the same
-solves alone, bit for bit.
+solves alone, bit for bit; one case per kernel family also in reverse and
+random scheduling order, with the same outputs bit for bit.
 """
 import concurrent.futures
 import glob
@@ -214,6 +215,9 @@ def test_complex64_lu_large_emulated(tmp_path_factory, config, L, Np):
 LIB_CASES = ["grad_small", "grad_blocked", "grad_fp32r", "grad_ldlt",
              "grad_eigh", "grad_tail", "adam", "dos", "factors", "noalloc",
              "server", "hmc"]
+# one case per kernel family, also run in reverse and random order
+ORDER_CASES = ["grad_small", "grad_fp32r", "grad_ldlt", "grad_eigh",
+               "grad_tail", "adam"]
 
 
 def _asan_runtime():
@@ -271,19 +275,23 @@ def lib_results(tmp_path_factory):
     env["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1"
     script = os.path.join(ROOT, "tests", "emu", "lib_cases.py")
 
-    def run(case):
+    def run(job):
+        case, order = job
+        e = dict(env, EMU_ORDER=str(order))
         r = subprocess.run([sys.executable, script, lib, case],
-                           capture_output=True, text=True, env=env,
+                           capture_output=True, text=True, env=e,
                            timeout=900)
-        return case, r
+        return job, r
 
+    jobs = [(c, 0) for c in LIB_CASES] + [(c, o) for c in ORDER_CASES
+                                          for o in (1, 2)]
     with concurrent.futures.ThreadPoolExecutor(max_workers=6) as ex:
-        return dict(ex.map(run, LIB_CASES))
+        return dict(ex.map(run, jobs))
 
 
 @pytest.mark.parametrize("case", LIB_CASES)
 def test_library_emulated(lib_results, case):
-    r = lib_results[case]
+    r = lib_results[(case, 0)]
     report = r.stdout + r.stderr
     assert "AddressSanitizer" not in report, report[-4000:]
     assert "EMU ERROR" not in report, report[-4000:]
@@ -295,3 +303,15 @@ def test_library_emulated(lib_results, case):
         assert err < tol, (case, name, err)
     for name, ok in out["bitwise"].items():
         assert ok, (case, name)
+
+
+@pytest.mark.parametrize("case", ORDER_CASES)
+def test_library_order_independent(lib_results, case):
+    """The same outputs, bit for bit, whether lanes and waves run forward,
+    in reverse or in a random order between synchronisation points."""
+    digests = []
+    for order in (0, 1, 2):
+        r = lib_results[(case, order)]
+        assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
+        digests.append(json.loads(r.stdout.strip().splitlines()[-1])["digest"])
+    assert digests[0] == digests[1] == digests[2], (case, digests)
