@@ -42,6 +42,8 @@ struct LuLds {
   T *unr, *uni;       // [NB][NB+1] -U_IJ, or U_JJ^-1
   T *tr_, *ti_;       // [NB*NB/2] scratch of the block inversion
   double* red;        // [NT] final reductions
+  double* hs;         // [Np] the matrix's diagonal h (read by generation)
+  int* nbr;           // [4][Np] row panel: the 4 lattice neighbours of a site
 };
 
 }  // namespace
@@ -59,6 +61,8 @@ size_t lu_lds_bytes(int Np, int NB, int waves, bool rp = false) {
     if (extra > 0) b += sizeof(T) * extra;
   }
   b += sizeof(int) * Np;
+  b += sizeof(double) * Np;                // h
+  if (rp) b += sizeof(int) * 4 * Np;       // neighbours
   b += sizeof(double) * 2 * waves + sizeof(int) * 2 * waves;
   b += sizeof(double) * 64 * waves;        // final reductions
   b += sizeof(T) * 4 * NB;                 // rA [2][NB] re, im
@@ -97,6 +101,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     double* dd = lds_raw;
     S.cmag = dd; dd += 2 * WAVES;
     S.red = dd; dd += NT;
+    S.hs = dd; dd += Np;
     T* d = reinterpret_cast<T*>(dd);
     S.mr = d; d += Np; S.mi = d; d += Np;
     S.rAr = d; d += 2 * NB; S.rAi = d; d += 2 * NB;
@@ -108,7 +113,8 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     if (kRP && d < S.xsr + WAVES * rp_stage_per_wave(WAVES)) d = S.xsr + WAVES * rp_stage_per_wave(WAVES);
     int* ip = reinterpret_cast<int*>(d);
     S.crowi = ip; ip += 2 * WAVES;
-    S.perm = ip;
+    S.perm = ip; ip += Np;
+    S.nbr = ip;
   }
 
   const MatDesc dsc = descs[b];
@@ -119,6 +125,20 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   T* Tb = tri + (size_t)b * nblk * 4 * NB * NB;   // [nblk][2][2][NB][NB]
 
   for (int p = tid; p < Np; p += NT) S.perm[p] = p;
+  // h once per matrix: generation reads it from LDS (a global load per row
+  // tile would put its latency on every block column)
+  for (int p = tid; p < N; p += NT) S.hs[p] = h[p];
+  // row panel: each site's neighbours (+x, -x, +y, -y) once per matrix, so
+  // that generating a block column divides by L nowhere
+  if constexpr (kRP) {
+    for (int r = tid; r < N; r += NT) {
+      const int x = r % L, y = r / L;
+      S.nbr[r] = (x + 1) % L + L * y;
+      S.nbr[Np + r] = (x + L - 1) % L + L * y;
+      S.nbr[2 * Np + r] = x + L * ((y + 1) % L);
+      S.nbr[3 * Np + r] = x + L * ((y + L - 1) % L);
+    }
+  }
   __syncthreads();
 
   V4 xr[RT][CT], xi[RT][CT];
@@ -145,12 +165,19 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
         int n0 = -1, n1 = -1, n2 = -1, n3 = -1;
         double dre = 0.0;
         if (r < N) {
-          const int x = r % L, y = r / L;
-          n0 = (x + 1) % L + L * y;
-          n1 = (x + L - 1) % L + L * y;
-          n2 = x + L * ((y + 1) % L);
-          n3 = x + L * ((y + L - 1) % L);
-          dre = dsc.zr - h[r];
+          if constexpr (kRP) {
+            n0 = S.nbr[r];
+            n1 = S.nbr[Np + r];
+            n2 = S.nbr[2 * Np + r];
+            n3 = S.nbr[3 * Np + r];
+          } else {
+            const int x = r % L, y = r / L;
+            n0 = (x + 1) % L + L * y;
+            n1 = (x + L - 1) % L + L * y;
+            n2 = x + L * ((y + 1) % L);
+            n3 = x + L * ((y + L - 1) % L);
+          }
+          dre = dsc.zr - S.hs[r];
         }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
