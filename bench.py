@@ -60,18 +60,18 @@ HBM_PEAK = 8000.0                       # GB/s
 # counters were taken on: a changed source reports null.
 TRAFFIC = {
     ("lu", "hubbard_20x20_T0.1", "fp64", "lu"): (
-        19.415e9, "k_factor.hip",
-        "8d8aef049a1a04cccc988f1a194076d2d5c85135afb741865279ef476868a581"),
+        19.896e9, "k_factor.hip",
+        "6ceab981287d54c76a56f45a669cdc31344a6e9317313338269fb0db00113ffa"),
     ("ldlt", "hubbard_20x20_T0.1", "fp64", "ldlt"): (
         8.093e9, "k_ldlt.hip",
         "4cf959a57de490a72fb2705cb64b0f9c8a9a37292161af1ff71b6f28f1ef2ca2"),
     # profiles/fp32r_hubbard_20x20.md, profiles/fp32r_ionic_48x48.md
     ("lu", "hubbard_20x20_T0.1", "fp32r", "lu"): (
-        8.442e9, "k_factor.hip",
-        "8d8aef049a1a04cccc988f1a194076d2d5c85135afb741865279ef476868a581"),
+        8.431e9, "k_factor.hip",
+        "6ceab981287d54c76a56f45a669cdc31344a6e9317313338269fb0db00113ffa"),
     ("trtri", "hubbard_20x20_T0.1", "fp32r", "lu"): (
-        8.615e9, "k_factor.hip",
-        "8d8aef049a1a04cccc988f1a194076d2d5c85135afb741865279ef476868a581"),
+        8.994e9, "k_factor.hip",
+        "6ceab981287d54c76a56f45a669cdc31344a6e9317313338269fb0db00113ffa"),
     ("wvgemm", "hubbard_20x20_T0.1", "fp32r", "lu"): (
         4.854e9, "k_refine.hip",
         "8a478518d1f480b6c3be0bc33e3b7f3901935e51e2e6a3c9061831831e5668f1"),
@@ -79,8 +79,8 @@ TRAFFIC = {
         1.483e9, "k_refine.hip",
         "8a478518d1f480b6c3be0bc33e3b7f3901935e51e2e6a3c9061831831e5668f1"),
     ("lu", "ionic_48x48", "fp32r", "lu"): (
-        1376.98e9, "k_factor.hip",
-        "8d8aef049a1a04cccc988f1a194076d2d5c85135afb741865279ef476868a581"),
+        1376.94e9, "k_factor.hip",
+        "6ceab981287d54c76a56f45a669cdc31344a6e9317313338269fb0db00113ffa"),
 }
 
 

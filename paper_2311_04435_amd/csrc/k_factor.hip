@@ -42,7 +42,7 @@ struct LuLds {
   T *unr, *uni;       // [NB][NB+1] -U_IJ, or U_JJ^-1
   T *tr_, *ti_;       // [NB*NB/2] scratch of the block inversion
   double* red;        // [NT] final reductions
-  double* hs;         // [Np] the matrix's diagonal h (read by generation)
+  double* hs;         // [Np] row panel: the matrix's diagonal h
   int* nbr;           // [4][Np] row panel: the 4 lattice neighbours of a site
 };
 
@@ -61,8 +61,7 @@ size_t lu_lds_bytes(int Np, int NB, int waves, bool rp = false) {
     if (extra > 0) b += sizeof(T) * extra;
   }
   b += sizeof(int) * Np;
-  b += sizeof(double) * Np;                // h
-  if (rp) b += sizeof(int) * 4 * Np;       // neighbours
+  if (rp) b += sizeof(double) * Np + sizeof(int) * 4 * Np;   // h, neighbours
   b += sizeof(double) * 2 * waves + sizeof(int) * 2 * waves;
   b += sizeof(double) * 64 * waves;        // final reductions
   b += sizeof(T) * 4 * NB;                 // rA [2][NB] re, im
@@ -101,7 +100,7 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
     double* dd = lds_raw;
     S.cmag = dd; dd += 2 * WAVES;
     S.red = dd; dd += NT;
-    S.hs = dd; dd += Np;
+    if constexpr (kRP) { S.hs = dd; dd += Np; }
     T* d = reinterpret_cast<T*>(dd);
     S.mr = d; d += Np; S.mi = d; d += Np;
     S.rAr = d; d += 2 * NB; S.rAi = d; d += 2 * NB;
@@ -125,12 +124,12 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
   T* Tb = tri + (size_t)b * nblk * 4 * NB * NB;   // [nblk][2][2][NB][NB]
 
   for (int p = tid; p < Np; p += NT) S.perm[p] = p;
-  // h once per matrix: generation reads it from LDS (a global load per row
-  // tile would put its latency on every block column)
-  for (int p = tid; p < N; p += NT) S.hs[p] = h[p];
-  // row panel: each site's neighbours (+x, -x, +y, -y) once per matrix, so
-  // that generating a block column divides by L nowhere
+  // row panel: h and each site's neighbours (+x, -x, +y, -y) once per
+  // matrix, so that generating a block column divides by L nowhere and loads
+  // nothing from global memory (the other instances keep their form: their
+  // register allocation, hundreds of spilled VGPRs, is slower with it)
   if constexpr (kRP) {
+    for (int p = tid; p < N; p += NT) S.hs[p] = h[p];
     for (int r = tid; r < N; r += NT) {
       const int x = r % L, y = r / L;
       S.nbr[r] = (x + 1) % L + L * y;
@@ -170,14 +169,15 @@ lu_kernel(const MatDesc* __restrict__ descs, const double* __restrict__ hbuf,
             n1 = S.nbr[Np + r];
             n2 = S.nbr[2 * Np + r];
             n3 = S.nbr[3 * Np + r];
+            dre = dsc.zr - S.hs[r];
           } else {
             const int x = r % L, y = r / L;
             n0 = (x + 1) % L + L * y;
             n1 = (x + L - 1) % L + L * y;
             n2 = x + L * ((y + 1) % L);
             n3 = x + L * ((y + L - 1) % L);
+            dre = dsc.zr - h[r];
           }
-          dre = dsc.zr - S.hs[r];
         }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
