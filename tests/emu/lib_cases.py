@@ -233,6 +233,10 @@ def case_hmc():
 CASES = {
     "grad_small": lambda: (grad_case(params(4, 16)), {}),
     "grad_blocked": lambda: (grad_case(params(10, 4)), {}),
+    # L = 18 (Np = 352): the row-panel LU instances of the 20x20 runs, and
+    # the complex64 inverse two workgroups per CU
+    "grad_rowpanel": lambda: (grad_case(params(18, 1)), {}),
+    "grad_rowpanel_fp32r": lambda: (grad_case(params(18, 1, precision=1)), {}),
     "grad_fp32r": lambda: (grad_case(params(10, 4, precision=1)), {}),
     "grad_ldlt": lambda: (grad_case(params(10, 4, factor=1)), {}),
     "grad_eigh": lambda: (grad_case(params(6, 8, factor=2)), {}),

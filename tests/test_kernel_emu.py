@@ -31,7 +31,8 @@ The whole library (every source under csrc/, host code included, with the
 stand-in HIP runtime of tests/emu/hip/hip_runtime.h) is also built as a
 shared object and driven through its C ABI by tests/emu/lib_cases.py in
 processes with the AddressSanitizer runtime preloaded: sca_grad on every
-route (fused, blocked FP64, refined FP32, L D L^T, spectral, moment tail),
+route (fused, blocked FP64 with the 4-wave and the row-panel instances,
+refined FP32, L D L^T, spectral, moment tail),
 sca_adam_solve, sca_dos, sca_hmc against the oracle; the autograd split and
 sca_grad_noalloc against sca_grad, and served requests against the same
 solves alone, bit for bit; one case per kernel family also in reverse and
@@ -182,19 +183,46 @@ def _tol(config):
     return (1e-12, 1e-10) if config.startswith("f32r") else (1e-6, 1e-5)
 
 
+ORDER_CASES_KERNELS = [("f64:1", 12, 160), ("f32r:3", 12, 160)]
+
+
+@pytest.fixture(scope="module")
+def kernel_results(emu_exe, tmp_path_factory):
+    """Every case below, run in parallel processes; each job's result or
+    the exception it raised."""
+    tmp = str(tmp_path_factory.mktemp("emu_runs"))
+    jobs = [(c, L, Np, 0) for c, L, Np in CASES]
+    jobs += [(c, L, Np, o) for c, L, Np in ORDER_CASES_KERNELS for o in (1, 2)]
+
+    def run(job):
+        c, L, Np, o = job
+        try:
+            return job, (run_case(emu_exe, tmp, c, L, Np, order=o), None)
+        except Exception as e:   # re-raised by the test that owns the job
+            return job, (None, e)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=6) as ex:
+        return dict(ex.map(run, jobs))
+
+
+def _result(kernel_results, job):
+    res, err = kernel_results[job]
+    if err is not None:
+        raise err
+    return res
+
+
 @pytest.mark.parametrize("config,L,Np", CASES)
-def test_factor_kernels_emulated(emu_exe, tmp_path, config, L, Np):
-    _, errs = run_case(emu_exe, str(tmp_path), config, L, Np)
+def test_factor_kernels_emulated(kernel_results, config, L, Np):
+    _, errs = _result(kernel_results, (config, L, Np, 0))
     t_lad, t_dg = _tol(config)
     for e_lad, e_dg in errs:
         assert e_lad < t_lad and e_dg < t_dg, (config, L, errs)
 
 
-@pytest.mark.parametrize("config,L,Np", [("f64:1", 12, 160),
-                                         ("f32r:3", 12, 160)])
-def test_factor_kernels_order_independent(emu_exe, tmp_path, config, L, Np):
-    outs = [run_case(emu_exe, str(tmp_path), config, L, Np, order=o)[0]
-            for o in (0, 1, 2)]
+@pytest.mark.parametrize("config,L,Np", ORDER_CASES_KERNELS)
+def test_factor_kernels_order_independent(kernel_results, config, L, Np):
+    outs = [_result(kernel_results, (config, L, Np, o))[0] for o in (0, 1, 2)]
     assert outs[0] == outs[1] == outs[2]
 
 
@@ -212,9 +240,9 @@ def test_complex64_lu_large_emulated(tmp_path_factory, config, L, Np):
 
 # ---- the whole library through its C ABI -----------------------------------
 
-LIB_CASES = ["grad_small", "grad_blocked", "grad_fp32r", "grad_ldlt",
-             "grad_eigh", "grad_tail", "adam", "dos", "factors", "noalloc",
-             "server", "hmc"]
+LIB_CASES = ["grad_small", "grad_blocked", "grad_rowpanel",
+             "grad_rowpanel_fp32r", "grad_fp32r", "grad_ldlt", "grad_eigh",
+             "grad_tail", "adam", "dos", "factors", "noalloc", "server", "hmc"]
 # one case per kernel family, also run in reverse and random order
 ORDER_CASES = ["grad_small", "grad_fp32r", "grad_ldlt", "grad_eigh",
                "grad_tail", "adam"]
@@ -298,7 +326,7 @@ def test_library_emulated(lib_results, case):
     assert r.returncode == 0, report[-4000:]
     out = json.loads(r.stdout.strip().splitlines()[-1])
     # FP64 routes: the 1e-10 parity bar; the refined FP32 route: 1e-6
-    tol = 1e-6 if case == "grad_fp32r" else 1e-10
+    tol = 1e-6 if case.endswith("fp32r") else 1e-10
     for name, err in out["errors"].items():
         assert err < tol, (case, name, err)
     for name, ok in out["bitwise"].items():
