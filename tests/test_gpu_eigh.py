@@ -147,6 +147,23 @@ def test_eigh_large_48x48(sca):
     assert e_g < 1e-10 and e_om < 1e-10
 
 
+def test_eigh_max_size_64x64(sca):
+    """N = 4096, the largest lattice the library takes (L <= 64): the
+    Householder instance for N > 2560 (40 columns per lane, only the
+    workgroups whose rows are still in play), bisection, inverse iteration
+    and the back-transformation at full size; Omega~ and the gradient
+    against route S."""
+    L = 64
+    p = sca.Params(L=L, U=4.0, T=0.1, n_max=32, delta=0.5, factor="eigh")
+    phi = synth.uniform(640, L * L, -0.5, 0.5)
+    g, o2 = sca.grad(p, cuda(phi))
+    om_t, gr = oracle.terms_spectral(L, p.t, p.U, p.delta, p.T, p.n_max, phi)
+    e_g = grad_err(g.cpu().numpy(), gr, phi, p.U)
+    e_om = abs(o2[1].item() - om_t) / abs(om_t)
+    print(f"64x64 eigh: Omega~ err {e_om:.2e}  grad err {e_g:.2e}")
+    assert e_g < 1e-10 and e_om < 1e-10
+
+
 def test_eigh_tail(sca):
     wl = synth.WORKLOADS["hubbard_20x20_T0.1"]
     p = sca.Params.from_dict(wl["params"], factor="eigh", tail=True)
