@@ -39,7 +39,7 @@ def rel_inf(a, b):
 
 # L = 10, 12, 16 use the 4-wave instance (N padded to 128/160/256), 18, 20
 # the 8-wave one (352, 416), 24 and 32 the 16-wide one (576, 1024).
-@pytest.mark.parametrize("L", [10, 12, 16, 18, 20, 24, 32])
+@pytest.mark.parametrize("L", [10, 12, 16, 18, 20, 22, 24, 32])
 def test_blocked_shifted_terms(sca, L):
     import torch
     p = sca.Params(L=L, U=4.0, T=0.1, n_max=512, delta=0.8)

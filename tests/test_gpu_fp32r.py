@@ -55,11 +55,12 @@ def grad_err(g, gr, phi, U):
 
 
 # N padded to a multiple of 32: L = 10, 12, 16 -> 4-wave instance (128, 160,
-# 256), 18, 20 -> 8 x 4 tiles, row panel (352, 416), 24, 28, 32 -> 8 x 8
-# tiles (576, 800, 1024), 40, 44, 48 -> 8 x 18 tiles with 16-wide blocks
-# (1600, 1952, 2304).  160, 352, 416, 800 and 1952 leave a partial 64 x 64
-# tile in the W V product.
-@pytest.mark.parametrize("L", [10, 12, 16, 18, 20, 24, 28, 32, 40, 44, 48])
+# 256), 18, 20 -> 8 x 4 tiles, row panel, with the inverse as 4 x 7 tiles two
+# workgroups per CU (352, 416), 22 -> 8 x 4 tiles and inverse, every row slot
+# filled (512), 24, 28, 32 -> 8 x 8 tiles (576, 800, 1024), 40, 44, 48 ->
+# 8 x 18 tiles with 16-wide blocks (1600, 1952, 2304).  160, 352, 416, 800
+# and 1952 leave a partial 64 x 64 tile in the W V product.
+@pytest.mark.parametrize("L", [10, 12, 16, 18, 20, 22, 24, 28, 32, 40, 44, 48])
 def test_fp32r_shifted_terms(sca, L):
     import torch
     p = sca.Params(L=L, U=4.0, T=0.1, n_max=512, delta=0.8, precision="fp32r")

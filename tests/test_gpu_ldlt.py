@@ -41,7 +41,7 @@ def grad_err(g, gr, phi, U):
                  max(np.max(np.abs(gr)), 2 * np.max(np.abs(phi)) / U))
 
 
-@pytest.mark.parametrize("L", [10, 12, 16, 18, 20, 24, 32])
+@pytest.mark.parametrize("L", [10, 12, 16, 18, 20, 22, 24, 32])
 def test_ldlt_shifted_terms(sca, L):
     import torch
     p = sca.Params(L=L, U=4.0, T=0.1, n_max=512, delta=0.8, factor="ldlt")
