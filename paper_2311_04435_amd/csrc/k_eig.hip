@@ -20,6 +20,10 @@
 //                      and p = tau A v of the workgroup's rows written for
 //                      the next launch.  H = Q T Q^T, Q = H_0 H_1 .. H_{N-2},
 //                      T tridiagonal (d, e).
+//   hh_tail_kernel     the last columns (trailing block of at most 160 rows)
+//                      in one workgroup of four waves per h vector, the
+//                      block in registers: three barriers per column instead
+//                      of a launch (every column when N <= 161).
 //   bisect_kernel      T splits where |e_i| <= 2 eps |T|; one wave per
 //                      eigenvalue: 64 Sturm counts per round (65-section),
 //                      ten rounds.
@@ -44,6 +48,7 @@
 #include <algorithm>
 #include <float.h>
 #include <math.h>
+#include "k_factor_common.h"
 #include "sca_common.h"
 #include "sca_kernels.h"
 #include "sca_profile.h"
@@ -54,6 +59,12 @@ namespace sca {
 namespace {
 
 constexpr int kRowsPerWg = 4;     // hh_step (N <= 512): one wave per row
+constexpr int kTailWaves = 4;     // hh_tail: waves of the one workgroup
+constexpr int kTailRows = 40;     // hh_tail: rows per wave
+constexpr int kTailKM = 3;        // hh_tail: column registers per row
+constexpr int kTailMax = kTailWaves * kTailRows;   // trailing block it keeps
+constexpr int kTailCols = 64 * kTailKM;             // columns the lanes span
+static_assert(kTailMax <= kTailCols, "rows and columns of the block");
 constexpr int kWy = 32;           // reflectors per compact WY block
 constexpr int kWyCols = 16;       // columns of Z per back-transform workgroup
 constexpr int kBisRounds = 10;    // 65^-10 of the Gershgorin width
@@ -295,6 +306,241 @@ hh_step_kernel(int N, int j, int first, EigBufs E) {
       vb[(4 + cur) * N + r] = ar[0];
     }
   }
+}
+
+// Sum over the 64 lanes, the same value in every lane: DPP inside each row
+// of 16 lanes, then the four row sums in a fixed order.
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) +
+         (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Householder steps j0 .. N-1, grid (1, nH), kTailWaves waves (one per
+// SIMD, so the work every wave repeats costs once per SIMD): the same
+// reflectors as hh_step_kernel (H_j = I - tau v v^T from column j of A_j),
+// for a trailing block small enough for one workgroup's registers: rows and
+// columns (j0, N), N - j0 - 1 <= kTailMax.  Wave w keeps rows
+// r = j0 + 1 + w + kTailWaves i (i < kTailRows), lane columns
+// c = j0 + 1 + lane + 64 k (k < kTailKM).  Per column j:
+//   column j of A_j (sx, double-buffered in LDS) gives alpha, |x|^2 and the
+//   reflector, formed by every wave;
+//   p = tau A_j v by columns over the wave's rows (A_j is symmetric), the
+//   waves' partial sums added in wave order;
+//   K = tau (p.v) / 2, w = p - K v, A_{j+1} = A_j - v w^T - w v^T on the rows
+//   and columns beyond j;
+//   column j+1 of A_{j+1} below the diagonal is copied into the other sx as
+//   row j+1 (symmetry), with its |x|^2, by the wave that keeps that row.
+// Rows and columns that are finished (at or before j) or past N take
+// v = w = 0, which leaves them unchanged and adds nothing to p; a wave skips
+// its groups of finished rows (uniform branches).
+// With j0 > 0 the reflector of column j0-1 is pending, as the launch of
+// column j0-1 left it: v, p, tau and column j0 of A_{j0-1}.
+__global__ void __launch_bounds__(kTailWaves * 64)
+hh_tail_kernel(int N, int j0, EigBufs E) {
+  constexpr int NT = kTailWaves * 64;
+  const int hv = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int base = j0 + 1;   // first row and column kept
+  const int m = N - base;    // rows and columns kept
+  const double* A = E.A + (size_t)hv * N * N;
+  const double* vb = E.vec + (size_t)hv * 6 * N;
+  __shared__ double sxb[2][kTailCols + 1];   // column of A_j, index q - j0
+  __shared__ double svp[2 * kTailCols];      // (v, p) at index c - base
+  __shared__ double part[kTailWaves][kTailCols];
+  __shared__ double ssq[2];                  // |x|^2 of the next column
+  __shared__ double sv0[kTailCols + 1], sp0[kTailCols + 1];   // pending v, p
+  const int ri1 = m > w ? (m - w + kTailWaves - 1) / kTailWaves : 0;
+  double a[kTailRows][kTailKM];
+#pragma unroll
+  for (int i = 0; i < kTailRows; ++i) {
+    const int r = base + w + kTailWaves * i;
+#pragma unroll
+    for (int k = 0; k < kTailKM; ++k) {
+      const int c = base + lane + 64 * k;
+      a[i][k] = (r < N && c < N) ? A[(size_t)r * N + c] : 0.0;
+    }
+  }
+  double* sx = sxb[0];
+  if (j0 > 0) {
+    const int prv = (j0 - 1) & 1;
+    const double tp = E.tau[2 * hv + prv];
+    for (int t = tid; t <= m; t += NT) {
+      sv0[t] = vb[prv * N + j0 + t];
+      sp0[t] = vb[(2 + prv) * N + j0 + t];
+      sx[t] = vb[(4 + prv) * N + j0 + t];
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int t = lane; t <= m; t += 64) s += sv0[t] * sp0[t];
+    const double K = 0.5 * tp * wave_sum_dpp(s);
+    // column j0 of A_j0 from the copy (each thread its own entries), then
+    // the kept rows
+    const double vj = sv0[0], wj = sp0[0] - K * sv0[0];
+    for (int t = tid; t <= m; t += NT) {
+      const double wq = sp0[t] - K * sv0[t];
+      sx[t] -= sv0[t] * wj + wq * vj;
+    }
+    double vc[kTailKM], wc[kTailKM];
+#pragma unroll
+    for (int k = 0; k < kTailKM; ++k) {
+      const int t = 1 + lane + 64 * k;
+      vc[k] = t <= m ? sv0[t] : 0.0;
+      wc[k] = t <= m ? sp0[t] - K * sv0[t] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kTailRows; ++i) {
+      if (i < ri1) {
+        const int t = 1 + w + kTailWaves * i;
+        const double vr = sv0[t], wr = sp0[t] - K * sv0[t];
+#pragma unroll
+        for (int k = 0; k < kTailKM; ++k) a[i][k] -= vr * wc[k] + wr * vc[k];
+      }
+    }
+  } else {
+    for (int q = tid; q < N; q += NT) sx[q] = A[(size_t)q * N];
+  }
+  __syncthreads();
+  // Per-row scalars (v_r, w_r) reach the rows' loops by readlane from the
+  // lane numbered like the row (lane i holds row i of the wave), so a row
+  // costs no LDS wait; rows are skipped in groups of kTailGrp.
+  constexpr int kTailGrp = 8;
+  static_assert(kTailRows % kTailGrp == 0 && kTailRows <= 64, "row groups");
+  const int tl = w + kTailWaves * lane;   // local index of this lane's row
+  int cur = 0;
+  for (int j = j0; j < N - 1; ++j) {
+    const double* sxc = sxb[cur];
+    double* sxn = sxb[cur ^ 1];
+    const int jl = j - j0;   // column j+1 is local column jl
+    // first row of this wave in play (t = w + kTailWaves i >= jl)
+    const int ri0 = jl > w ? (jl - w + kTailWaves - 1) / kTailWaves : 0;
+    // reflector of column j from x = column j of A_j below the diagonal
+    const double alpha = sxc[jl + 1];
+    double s2;
+    if (j == j0) {
+      s2 = 0.0;
+      for (int q = j + 2 + lane; q < N; q += 64) {
+        const double x = sxc[q - j0];
+        s2 += x * x;
+      }
+      s2 = wave_sum_dpp(s2);
+    } else {
+      s2 = ssq[cur];
+    }
+    double tau, beta, scale;
+    if (s2 == 0.0) {
+      tau = 0.0; beta = alpha; scale = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + s2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // v at local index t: 0 before jl, 1 at jl, x scale beyond, 0 past N
+    auto vloc = [&](int t) {
+      const double x = sxc[t + 1];
+      return (t > jl && t < m) ? x * scale : (t == jl ? 1.0 : 0.0);
+    };
+    if (tid == 0) {
+      E.d[(size_t)hv * N + j] = sxc[jl];
+      E.e[(size_t)hv * N + j] = beta;
+      E.taus[(size_t)hv * N + j] = tau;
+    }
+    double* vrow = E.V + ((size_t)hv * N + j) * N;
+    for (int q = tid; q < N; q += NT)
+      vrow[q] = q > j + 1 ? sxc[q - j0] * scale : (q == j + 1 ? 1.0 : 0.0);
+    // p = tau A_j v: the wave's rows, by columns
+    const double vl = lane < kTailRows ? vloc(tl) : 0.0;
+    double pc[kTailKM];
+#pragma unroll
+    for (int k = 0; k < kTailKM; ++k) pc[k] = 0.0;
+#pragma unroll
+    for (int g = 0; g < kTailRows; g += kTailGrp) {
+      if (g + kTailGrp > ri0) {
+#pragma unroll
+        for (int i = g; i < g + kTailGrp; ++i) {
+          const double vr = readlane_d(vl, i);
+#pragma unroll
+          for (int k = 0; k < kTailKM; ++k) pc[k] = fma(a[i][k], vr, pc[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTailKM; ++k) part[w][lane + 64 * k] = pc[k];
+    __syncthreads();
+    // v and p side by side for the update's reads
+    if (tid < m) {
+      double s = part[0][tid];
+#pragma unroll
+      for (int ww = 1; ww < kTailWaves; ++ww) s += part[ww][tid];
+      svp[2 * tid] = vloc(tid);
+      svp[2 * tid + 1] = tau * s;
+    }
+    __syncthreads();
+    // K = tau (p.v) / 2, then A_{j+1} = A_j - v w^T - w v^T beyond j
+    double pv = 0.0;
+    for (int t = jl + lane; t < m; t += 64) pv += svp[2 * t] * svp[2 * t + 1];
+    const double K = 0.5 * tau * wave_sum_dpp(pv);
+    double vc[kTailKM], wc[kTailKM];
+#pragma unroll
+    for (int k = 0; k < kTailKM; ++k) {
+      const int t = lane + 64 * k;
+      const bool act = t >= jl && t < m;
+      vc[k] = act ? svp[2 * t] : 0.0;
+      wc[k] = act ? svp[2 * t + 1] - K * vc[k] : 0.0;
+    }
+    double rv = 0.0, rw = 0.0;   // v and w of this lane's row
+    if (lane < kTailRows && tl >= jl && tl < m) {
+      rv = svp[2 * tl];
+      rw = svp[2 * tl + 1] - K * rv;
+    }
+#pragma unroll
+    for (int g = 0; g < kTailRows; g += kTailGrp) {
+      if (g + kTailGrp > ri0) {
+#pragma unroll
+        for (int i = g; i < g + kTailGrp; ++i) {
+          const double vr = readlane_d(rv, i), wr = readlane_d(rw, i);
+#pragma unroll
+          for (int k = 0; k < kTailKM; ++k)
+            a[i][k] = fma(-wr, vc[k], fma(-vr, wc[k], a[i][k]));
+        }
+      }
+    }
+    // column j+1 of A_{j+1} below the diagonal as row j+1 (A_{j+1} is
+    // symmetric): row jl / kTailWaves of wave jl % kTailWaves, every lane
+    // its columns; that wave also forms the next |x|^2 (columns beyond j+2)
+    if (w == jl % kTailWaves) {
+      const int is = jl / kTailWaves;
+      double sq = 0.0;
+#pragma unroll
+      for (int g = 0; g < kTailRows; g += kTailGrp) {
+        if (is >= g && is < g + kTailGrp) {
+#pragma unroll
+          for (int i = g; i < g + kTailGrp; ++i) {
+            if (i == is) {
+#pragma unroll
+              for (int k = 0; k < kTailKM; ++k) {
+                const int t = lane + 64 * k;
+                const double x = a[i][k];
+                if (t >= jl && t < m) sxn[t + 1] = x;
+                sq = (t >= jl + 2 && t < m) ? fma(x, x, sq) : sq;
+              }
+            }
+          }
+        }
+      }
+      sq = wave_sum_dpp(sq);
+      if (lane == 0) ssq[cur ^ 1] = sq;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  // last diagonal entry; no reflector
+  if (tid == 0) E.d[(size_t)hv * N + N - 1] = sxb[cur][N - 1 - j0];
 }
 
 // Sturm count of T_blk - x (rows [b0, b1)): eigenvalues below x.
@@ -1032,11 +1278,16 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
   // above N = 1024 only the workgroups that hold rows below j (the others'
   // rows are finished; workgroup 0 of each launch also writes the
   // reflector): 13% less time at 2304, 2% more at 400 and 1024, as measured
-  for (int j = 0; j < N; ++j) {
+  // the last columns in one launch, once the trailing block fits one
+  // workgroup's registers
+  const int j0 = std::max(0, N - 1 - kTailMax);
+  for (int j = 0; j < j0; ++j) {
     const int first = N > 1024 ? std::min((j + 1) / wv, nrow - 1) : 0;
     hipLaunchKernelGGL(kern, dim3(nrow - first, nH), dim3(wv * 64),
                        sizeof(double) * 3 * N, st, N, j, first, E);
   }
+  hipLaunchKernelGGL(hh_tail_kernel, dim3(1, nH), dim3(kTailWaves * 64), 0,
+                     st, N, j0, E);
   mark_end(K_TRIDIAG, st);
   mark_begin(K_SPECTRUM, st);
   hipLaunchKernelGGL(bisect_kernel, dim3((N + 3) / 4, nH), dim3(256),

@@ -1,6 +1,7 @@
 // Device helpers shared by the factorisation kernels (k_factor.hip,
-// k_ldlt.hip): the MFMA of each element type, a double readlane, and the
-// inverses of the two triangles of a diagonal block.
+// k_ldlt.hip): the MFMA of each element type, a double readlane, DPP moves
+// inside rows of 16 lanes (also the spectral route's wave sums, k_eig.hip),
+// and the inverses of the two triangles of a diagonal block.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <type_traits>

@@ -240,6 +240,9 @@ CASES = {
     "grad_fp32r": lambda: (grad_case(params(10, 4, precision=1)), {}),
     "grad_ldlt": lambda: (grad_case(params(10, 4, factor=1)), {}),
     "grad_eigh": lambda: (grad_case(params(6, 8, factor=2)), {}),
+    # L = 14 (N = 196): Householder launches for the first columns, then the
+    # one-workgroup kernel for the last 160
+    "grad_eigh_chain": lambda: (grad_case(params(14, 1, factor=2)), {}),
     "grad_tail": lambda: (grad_case(params(6, 64, tail=1)), {}),
     "adam": case_adam,
     "dos": case_dos,

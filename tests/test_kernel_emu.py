@@ -242,7 +242,8 @@ def test_complex64_lu_large_emulated(tmp_path_factory, config, L, Np):
 
 LIB_CASES = ["grad_small", "grad_blocked", "grad_rowpanel",
              "grad_rowpanel_fp32r", "grad_fp32r", "grad_ldlt", "grad_eigh",
-             "grad_tail", "adam", "dos", "factors", "noalloc", "server", "hmc"]
+             "grad_eigh_chain", "grad_tail", "adam", "dos", "factors",
+             "noalloc", "server", "hmc"]
 # one case per kernel family, also run in reverse and random order
 ORDER_CASES = ["grad_small", "grad_fp32r", "grad_ldlt", "grad_eigh",
                "grad_tail", "adam"]
