@@ -37,12 +37,12 @@
 //                      order (block Gram-Schmidt over rows, two passes).
 //   wy_t_kernel        compact WY factor T of each block of 32 reflectors:
 //                      H_j0 .. H_j0+31 = I - V T V^T (Schreiber & Van Loan)
-//   wy_apply_kernel    psi = Q Z in place: the blocks applied to Z from the
-//                      last to the first, each workgroup on its own slice
-//                      of 16 columns (no dependency between workgroups),
-//                      V^T Z and V W2 on the f64 MFMA;
-//                      wy_apply_lds_kernel for N <= 512 keeps a 4-column
-//                      slice of Z and each block of V in LDS.
+//   wy_apply_reg_kernel psi = Q Z in place: the blocks applied to Z from
+//                      the last to the first, each workgroup on its own
+//                      slice of 16 columns (no dependency between
+//                      workgroups), the slice held in MFMA accumulators,
+//                      V^T Z and V W2 on the f64 MFMA (N <= 2304;
+//                      wy_apply_kernel above, the slice staged through LDS).
 //   expand_kernel      dg[b][i] = sum_k psi_k(i)^2 / (z_b - lambda_k)
 //   lad_kernel         lad[b] = sum_k ln|z_b - lambda_k|, growth[b] = 1
 #include <algorithm>
@@ -1006,7 +1006,7 @@ wy_t_kernel(int N, EigBufs E) {
 // g*16+n holds row g+4e).  Each 64-row chunk of V and Z is staged in LDS:
 // W = V^T Z takes the chunk's rows in steps of 4 split over the waves
 // (partial sums reduced through LDS); Z -= V W2 gives each wave one
-// 16-row tile.
+// 16-row tile.  Used above N = 2304 (wy_apply_reg_kernel below).
 __global__ void __launch_bounds__(256)
 wy_apply_kernel(int N, EigBufs E) {
   typedef double v4 __attribute__((ext_vector_type(4)));
@@ -1088,77 +1088,139 @@ wy_apply_kernel(int N, EigBufs E) {
   }
 }
 
-// N <= kWyLdsMax: the same back-transformation with the workgroup's slice of
-// Z (4 columns) resident in LDS for the whole kernel and each block of V
-// loaded into LDS once (one round of global loads per block instead of one
-// per 64-row chunk and phase).  Thread roles: W entries (i, k) = ((t >> 1)
-// >> 2, (t >> 1) & 3) over rows of parity t & 1; Z entries (rows
-// j0 + 1 + (t >> 2) + 64 m, column t & 3).
-constexpr int kWyLdsMax = 512;
-constexpr int kWyLdsCols = 4;
-__host__ __device__ constexpr size_t wy_lds_bytes(int N) {
-  return sizeof(double) * ((size_t)(kWy + kWyLdsCols) * N +
-                           kWy * (kWy + 1) + 2 * kWy * kWyLdsCols);
-}
-__global__ void __launch_bounds__(256)
-wy_apply_lds_kernel(int N, EigBufs E) {
+// grid (ceil(N / 16), nH), WAVES * 64 threads, N <= 16 * WAVES * TPW: the
+// back-transformation of wy_apply_kernel with the slice Z[:, k0 .. k0+16)
+// resident in MFMA accumulators for the whole kernel.  Wave w keeps the row
+// tiles t = w + WAVES s (s < TPW); element e of lane g*16+n holds
+// Z[16t + g + 4e][k0 + n], which is also the B operand of the k step over
+// the tile's rows 4e .. 4e+3.  Per block of reflectors, last first:
+//   W = V^T Z: per k step of each tile, A = V^T from global memory (the
+//   block's two halves of 16 reflectors), B = element e of the tile; the
+//   waves' partial W added in wave order through LDS;
+//   W2 = T W in LDS;
+//   Z -= V W2 on each tile: A = the tile's rows of V, B = W2.
+// Tiles above the block's first row take V = 0 there (exact zeros, stored),
+// so every tile runs the same code.  (Loading a tile's operands one to
+// three tiles ahead measured no faster: the waves sharing a SIMD already
+// cover the loads.)
+template <int TPW, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64)
+wy_apply_reg_kernel(int N, EigBufs E) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  constexpr int NT = WAVES * 64;
   const int hv = blockIdx.y, tid = threadIdx.x;
-  const int k0 = blockIdx.x * kWyLdsCols;
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, q = lane & 15;
+  const int k0 = blockIdx.x * 16;
   const int nref = N - 1, nwy = (nref + kWy - 1) / kWy;
   const double* V = E.V + (size_t)hv * N * N;
   double* Z = E.A + (size_t)hv * N * N;
-  extern __shared__ double sm[];
-  double* vsb = sm;                                  // [kWy][N]
-  double* zs = vsb + (size_t)kWy * N;                // [N][4]
-  double* ts = zs + (size_t)kWyLdsCols * N;          // [kWy][kWy + 1]
-  double* ws = ts + kWy * (kWy + 1);                 // [kWy][4]
-  double* w2 = ws + kWy * kWyLdsCols;                // [kWy][4]
-  for (int u = tid; u < N * kWyLdsCols; u += 256) {
-    const int r = u >> 2, kk = u & 3, c = k0 + kk;
-    zs[u] = c < N ? Z[(size_t)r * N + c] : 0.0;
+  __shared__ double wp[WAVES][kWy][17];   // per-wave partial W
+  __shared__ double ws[kWy][17];          // W
+  __shared__ double w2[kWy][17];
+  __shared__ double ts[kWy][kWy + 1];
+  const int c = k0 + q;
+  v4 z[TPW];
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    const int t = w + WAVES * s;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * t + g + 4 * e;
+      z[s][e] = (r < N && c < N) ? Z[(size_t)r * N + c] : 0.0;
+    }
   }
-  const int pi = (tid >> 1) >> 2, pk = (tid >> 1) & 3, ph = tid & 1;
-  const int zk = tid & 3, zr = tid >> 2;
   for (int blk = nwy - 1; blk >= 0; --blk) {
-    const int j0 = blk * kWy, nb = min(kWy, nref - j0), r0 = j0 + 1;
-    const int nr = N - r0;
+    const int j0 = blk * kWy, nb = min(kWy, nref - j0);
     const double* Tg = E.Tb + (((size_t)hv * nwy + blk) * kWy) * kWy;
-    __syncthreads();   // previous block done with vsb, ws, w2
-    for (int u = tid; u < kWy * kWy; u += 256) ts[(u / kWy) * (kWy + 1) + u % kWy] = Tg[u];
-    for (int u = tid; u < kWy * nr; u += 256) {
-      const int ii = u / nr, rr = u - ii * nr;
-      vsb[ii * N + rr] = ii < nb ? V[(size_t)(j0 + ii) * N + r0 + rr] : 0.0;
+    for (int u = tid; u < kWy * kWy; u += NT) ts[u / kWy][u % kWy] = Tg[u];
+    // Loads read clamped, in-bounds positions and zero what lies outside
+    // the block or past N afterwards (no branches around them); the tile's
+    // row offset is made opaque so that the compiler forms each tile's
+    // addresses at the tile, not all tiles' at once.
+    const double* pa = V + (size_t)min(j0 + q, N - 1) * N;
+    const double* pb = V + (size_t)min(j0 + 16 + q, N - 1) * N;
+    const bool oka = q < nb, okb = 16 + q < nb;
+    auto load_w = [&](int sx, double* a0, double* a1) {
+      int r0 = 16 * (w + WAVES * sx) + g;
+      asm volatile("" : "+v"(r0));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + 4 * e, rc = min(r, N - 1);
+        const double x0 = pa[rc], x1 = pb[rc];
+        a0[e] = (oka && r < N) ? x0 : 0.0;
+        a1[e] = (okb && r < N) ? x1 : 0.0;
+      }
+    };
+    // W = V^T Z
+    v4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+      double a0[4], a1[4];
+      load_w(s, a0, a1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[e], z[s][e], c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[e], z[s][e], c1, 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      wp[w][g + 4 * e][q] = c0[e];
+      wp[w][16 + g + 4 * e][q] = c1[e];
     }
     __syncthreads();
-    // W = V^T Z
-    double a = 0.0;
-    for (int rr = ph; rr < nr; rr += 2)
-      a = fma(vsb[pi * N + rr], zs[(r0 + rr) * kWyLdsCols + pk], a);
-    a += __shfl_xor(a, 1);
-    if (ph == 0) ws[pi * kWyLdsCols + pk] = a;
+    // W = the waves' parts added in wave order, then W2 = T W (T upper
+    // triangular)
+    for (int u = tid; u < kWy * 16; u += NT) {
+      const int i = u >> 4, n = u & 15;
+      double wv = wp[0][i][n];
+#pragma unroll
+      for (int ww = 1; ww < WAVES; ++ww) wv += wp[ww][i][n];
+      ws[i][n] = wv;
+    }
     __syncthreads();
-    // W2 = T W
-    if (tid < kWy * kWyLdsCols) {
-      const int i = tid >> 2, k = tid & 3;
+    for (int u = tid; u < kWy * 16; u += NT) {
+      const int i = u >> 4, n = u & 15;
       double b = 0.0;
-      for (int mm = i; mm < kWy; ++mm)
-        b = fma(ts[i * (kWy + 1) + mm], ws[mm * kWyLdsCols + k], b);
-      w2[i * kWyLdsCols + k] = b;
+      for (int mm = i; mm < kWy; ++mm) b = fma(ts[i][mm], ws[mm][n], b);
+      w2[i][n] = b;
     }
     __syncthreads();
     // Z -= V W2
-    for (int rr = zr; rr < nr; rr += 64) {
-      double acc = 0.0;
-#pragma unroll 8
-      for (int ii = 0; ii < kWy; ++ii)
-        acc = fma(vsb[ii * N + rr], w2[ii * kWyLdsCols + zk], acc);
-      zs[(r0 + rr) * kWyLdsCols + zk] -= acc;
+    double bw[kWy / 4];
+#pragma unroll
+    for (int ks = 0; ks < kWy / 4; ++ks) bw[ks] = w2[4 * ks + g][q];
+    auto load_z = [&](int sx, double* a) {
+      int r = 16 * (w + WAVES * sx) + q;
+      asm volatile("" : "+v"(r));
+      const int rc = min(r, N - 1);
+#pragma unroll
+      for (int ks = 0; ks < kWy / 4; ++ks) {
+        const int k = 4 * ks + g;
+        const double x = V[(size_t)min(j0 + k, N - 1) * N + rc];
+        a[ks] = (k < nb && r < N) ? x : 0.0;
+      }
+    };
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+      double a[kWy / 4];
+      load_z(s, a);
+#pragma unroll
+      for (int ks = 0; ks < kWy / 4; ++ks)
+        z[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ks], bw[ks], z[s], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    __syncthreads();   // ts, wp and w2 are rewritten by the next block
   }
-  __syncthreads();
-  for (int u = tid; u < N * kWyLdsCols; u += 256) {
-    const int r = u >> 2, kk = u & 3, c = k0 + kk;
-    if (c < N) Z[(size_t)r * N + c] = zs[u];
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    const int t = w + WAVES * s;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * t + g + 4 * e;
+      if (r < N && c < N) Z[(size_t)r * N + c] = z[s][e];
+    }
   }
 }
 
@@ -1306,13 +1368,18 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
                      E);
   const int nwy = (N - 1 + kWy - 1) / kWy;
   hipLaunchKernelGGL(wy_t_kernel, dim3(nwy, nH), dim3(256), 0, st, N, E);
-  if (N <= kWyLdsMax) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(wy_apply_lds_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)wy_lds_bytes(N));
-    hipLaunchKernelGGL(wy_apply_lds_kernel,
-                       dim3((N + kWyLdsCols - 1) / kWyLdsCols, nH), dim3(256),
-                       wy_lds_bytes(N), st, N, E);
+  // Z in registers up to N = 2304 (both spins, as measured against Z
+  // staged through LDS per block: 0.18 -> 0.175 ms at N = 400, 1.72 -> 0.80
+  // at 1024, 10.8 -> 8.3 at 2304; the shapes are the fastest of those tried)
+  if (N <= 512) {
+    hipLaunchKernelGGL((wy_apply_reg_kernel<2, 16>), dim3((N + 15) / 16, nH),
+                       dim3(1024), 0, st, N, E);
+  } else if (N <= 1024) {
+    hipLaunchKernelGGL((wy_apply_reg_kernel<4, 16>), dim3((N + 15) / 16, nH),
+                       dim3(1024), 0, st, N, E);
+  } else if (N <= 2304) {
+    hipLaunchKernelGGL((wy_apply_reg_kernel<12, 12>), dim3((N + 15) / 16, nH),
+                       dim3(768), 0, st, N, E);
   } else {
     hipLaunchKernelGGL(wy_apply_kernel, dim3((N + kWyCols - 1) / kWyCols, nH),
                        dim3(256), 0, st, N, E);

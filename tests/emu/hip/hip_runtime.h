@@ -39,9 +39,9 @@
 #define __builtin_amdgcn_readfirstlane(v) ::emu::readfirstlane((v))
 #define __builtin_amdgcn_update_dpp ::emu::update_dpp
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) \
-  ::emu::mfma<decltype(c), double, true>((a), (b), (c))
+  ::emu::mfma<std::decay_t<decltype(c)>, double, true>((a), (b), (c))
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) \
-  ::emu::mfma<decltype(c), float, false>((a), (b), (c))
+  ::emu::mfma<std::decay_t<decltype(c)>, float, false>((a), (b), (c))
 #define __shfl(...) ::emu::shfl(__VA_ARGS__)
 #define __shfl_xor(...) ::emu::shfl_xor(__VA_ARGS__)
 #define __shfl_up(...) ::emu::shfl_up(__VA_ARGS__)
