@@ -45,7 +45,11 @@ def grad_err(g, gr, phi, U):
     return float(np.max(np.abs(g - gr)) / scale)
 
 
-@pytest.mark.parametrize("L", [2, 4, 6, 8, 10, 14, 20, 32])
+# N = L^2: up to 161 the one-workgroup Householder kernel does every column
+# (L <= 12), beyond it the last 160; the back-transformation keeps Z in
+# registers as 2 tiles x 16 waves (N <= 512: L <= 22), 4 x 16 (L <= 32),
+# 12 x 12 (L <= 48: L = 34 here).
+@pytest.mark.parametrize("L", [2, 4, 6, 8, 10, 12, 14, 16, 20, 22, 24, 32, 34])
 def test_eigh_shifted_terms(sca, L):
     import torch
     p = sca.Params(L=L, U=4.0, T=0.1, n_max=512, delta=0.8, factor="eigh")
