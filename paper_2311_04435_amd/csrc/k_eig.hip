@@ -12,7 +12,8 @@
 // iteration scheme (Golub & Van Loan, Sec. 8.3-8.4; LAPACK's dsytrd, dstebz,
 // dstein describe the same steps):
 //   eig_init_kernel    dense H per h vector
-//   hh_step_kernel     one launch per column j: the pending reflector of
+//   hh_step_kernel     one launch per column j while the trailing block
+//                      exceeds 160 rows: the pending reflector of
 //                      column j-1 is applied to the trailing block of the
 //                      workgroup's rows; column j is formed from the
 //                      previous launch's copy, its reflector built
