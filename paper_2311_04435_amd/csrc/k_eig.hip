@@ -1100,9 +1100,10 @@ wy_apply_kernel(int N, EigBufs E) {
 //   waves' partial W added in wave order through LDS;
 //   W2 = T W in LDS;
 //   Z -= V W2 on each tile: A = the tile's rows of V, B = W2.
-// Tiles above the block's first row take V = 0 there (exact zeros, stored),
-// so every tile runs the same code.  (Loading a tile's operands one to
-// three tiles ahead measured no faster: the waves sharing a SIMD already
+// A wave skips its tiles wholly above the block's first row (the block's V
+// is zero there), a uniform branch per tile: half the MFMA work of the
+// whole slice, 0.80 -> 0.48 ms at N = 1024.  (Loading a tile's operands one
+// to three tiles ahead measured no faster: the waves sharing a SIMD already
 // cover the loads.)
 template <int TPW, int WAVES>
 __global__ void __launch_bounds__(WAVES * 64)
@@ -1153,9 +1154,14 @@ wy_apply_reg_kernel(int N, EigBufs E) {
       }
     };
     // W = V^T Z
+    // tiles wholly above the block's first row (all of V zero there) are
+    // skipped: this wave's tiles s >= slo
+    const int tlo = (j0 + 1) >> 4;
+    const int slo = tlo > w ? (tlo - w + WAVES - 1) / WAVES : 0;
     v4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
+      if (s < slo) continue;
       double a0[4], a1[4];
       load_w(s, a0, a1);
 #pragma unroll
@@ -1205,6 +1211,7 @@ wy_apply_reg_kernel(int N, EigBufs E) {
     };
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
+      if (s < slo) continue;
       double a[kWy / 4];
       load_z(s, a);
 #pragma unroll
@@ -1370,8 +1377,8 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
   const int nwy = (N - 1 + kWy - 1) / kWy;
   hipLaunchKernelGGL(wy_t_kernel, dim3(nwy, nH), dim3(256), 0, st, N, E);
   // Z in registers up to N = 2304 (both spins, as measured against Z
-  // staged through LDS per block: 0.18 -> 0.175 ms at N = 400, 1.72 -> 0.80
-  // at 1024, 10.8 -> 8.3 at 2304; the shapes are the fastest of those tried)
+  // staged through LDS per block: 0.18 -> 0.13 ms at N = 400, 1.72 -> 0.48
+  // at 1024, 10.8 -> 4.6 at 2304; the shapes are the fastest of those tried)
   if (N <= 512) {
     hipLaunchKernelGGL((wy_apply_reg_kernel<2, 16>), dim3((N + 15) / 16, nH),
                        dim3(1024), 0, st, N, E);
