@@ -30,9 +30,9 @@
 //                      ten rounds.
 //   invit_kernel       one lane per eigenvalue: pivoted LU of T_blk - lambda,
 //                      three solves from a counter-hashed start vector
-//                      (invit_lds_kernel for N <= 512: one wave per
-//                      eigenvalue with the block of T and the factors in
-//                      LDS, the same arithmetic).
+//                      (invit_reg_kernel for N <= 1024: one wave per
+//                      eigenvalue with the factors and the iterate in
+//                      registers, the same arithmetic).
 //   mgs_kernel         eigenvalues of one block closer than 1e-4 |T_blk| form
 //                      a cluster; its vectors are orthonormalised in index
 //                      order (block Gram-Schmidt over rows, two passes).
@@ -781,19 +781,22 @@ invit_kernel(int N, EigBufs E) {
   for (int i = 0; i < n; ++i) x[(size_t)i * N] *= f;
 }
 
-// grid (N, nH), 64 threads: one wave per eigenvalue t, for N up to
-// kInvLdsMax.  The same iteration as invit_kernel (identical arithmetic and
-// start vector), with the block of T, the factors and the iterate in LDS:
-// lane 0 runs the serial recurrences, the wave copies in and out.
-// Above this the LDS (57 N bytes) leaves too few waves per CU to cover the
-// chains' latency and the lane-per-eigenvalue kernel is faster (measured at
-// N = 1024 and 2304).
-constexpr int kInvLdsMax = 512;
-__host__ __device__ constexpr size_t invit_lds_bytes(int N) {
-  return sizeof(double) * 7 * (size_t)N + (size_t)N;
-}
+// grid (N, nH), 64 threads: one wave per eigenvalue t, for N <= 64 SPL.  The
+// iteration of invit_kernel (the same arithmetic and start vector) with the
+// factors and the iterate in registers: lane l keeps rows
+// SPL l .. SPL l + SPL - 1, and the serial recurrences, run by every lane on
+// the same values, take a row's entries with readlane and put them back
+// with a select on the lane (nothing on the chain waits for memory).  The
+// backward solve starts at row n-1 with the two later rows' values zero,
+// which gives its first two rows exactly (the extra terms are +-0).
+// Against the same iteration with the block of T, the factors and the
+// iterate in LDS (lane 0 running the recurrences; bitwise the same output):
+// 0.381 -> 0.247 ms at N = 400, 2.81 -> 1.41 ms at 1024; the
+// lane-per-eigenvalue kernel took 1.74 ms at 1024 (both spins, as
+// measured).
+template <int SPL>
 __global__ void __launch_bounds__(64)
-invit_lds_kernel(int N, EigBufs E) {
+invit_reg_kernel(int N, EigBufs E) {
   const int t = blockIdx.x, hv = blockIdx.y, lane = threadIdx.x;
   const size_t o = (size_t)hv * N;
   const int b0 = E.bnd[o * 2 + t], b1 = E.bnd[o * 2 + N + t];
@@ -806,88 +809,131 @@ invit_lds_kernel(int N, EigBufs E) {
     return;
   }
   extern __shared__ double sm[];
-  double* __restrict__ sd = sm;
+  double* __restrict__ sd = sm;       // d, e of the block, then x
   double* __restrict__ se = sd + n;
-  double* __restrict__ U0 = se + n;
-  double* __restrict__ U1 = U0 + n;
-  double* __restrict__ U2 = U1 + n;
-  double* __restrict__ Mm = U2 + n;
-  double* __restrict__ x = Mm + n;
-  unsigned char* __restrict__ Pv = reinterpret_cast<unsigned char*>(x + n);
-  __shared__ double sc_s;
+  double* __restrict__ xs = se + n;
   const double lam = E.lam[o + t], bn = E.bnorm[o + t];
   const unsigned long long seed = (unsigned long long)t << 32;
   for (int i = lane; i < n; i += 64) {
     sd[i] = E.d[o + b0 + i];
     se[i] = E.e[o + b0 + i];
-    x[i] = hash_uniform(seed | (unsigned)i);
+  }
+  double rx[SPL], ru0[SPL], ru1[SPL], ru2[SPL], rm[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int i = SPL * lane + s;
+    rx[s] = i < n ? hash_uniform(seed | (unsigned)i) : 0.0;
+    ru0[s] = 0.0; ru1[s] = 0.0; ru2[s] = 0.0; rm[s] = 0.0;
+  }
+  int rpv = 0;   // bit s: row SPL lane + s pivoted
+  // lane dst takes v (the same value in every lane), the others keep old
+  auto put = [&](double old, double v, int dst) { return lane == dst ? v : old; };
+  __syncthreads();
+  const int nblk = (n + SPL - 1) / SPL;
+  // elimination; the current row holds (cd, cs) at columns (i, i+1)
+  const double tol = kEps * bn;
+  double cd = sd[0] - lam, cs = se[0];
+  for (int b = 0; b < nblk; ++b) {
+    int bits = 0;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      const int i = SPL * b + s;
+      if (i < n - 1) {
+        const double ci = se[i];
+        const double an = sd[i + 1] - lam;
+        const double bnx = i + 1 < n - 1 ? se[i + 1] : 0.0;
+        const bool pv = fabs(ci) > fabs(cd);
+        double u0, u1, u2, m;
+        if (pv) {
+          u0 = ci; u1 = an; u2 = bnx;
+          m = cd / ci;
+          const double ncd = cs - m * an;
+          cs = -m * bnx;
+          cd = ncd;
+        } else {
+          if (cd == 0.0) cd = tol;
+          u0 = cd; u1 = cs; u2 = 0.0;
+          m = ci / cd;
+          cd = an - m * cs;
+          cs = bnx;
+        }
+        if (fabs(u0) < tol) u0 = u0 >= 0.0 ? tol : -tol;
+        ru0[s] = put(ru0[s], 1.0 / u0, b);
+        ru1[s] = put(ru1[s], u1, b);
+        ru2[s] = put(ru2[s], u2, b);
+        rm[s] = put(rm[s], m, b);
+        bits |= pv ? 1 << s : 0;
+      }
+    }
+    rpv = lane == b ? bits : rpv;
+  }
+  if (fabs(cd) < tol) cd = cd >= 0.0 ? tol : -tol;
+  {
+    const int i = n - 1, b = i / SPL;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s)
+      if (s == i % SPL) ru0[s] = put(ru0[s], 1.0 / cd, b);
+  }
+  const int nf = n - 1;
+  double sc = 1.0;
+  for (int it = 0; it < kInvIters; ++it) {
+    // forward: L^-1 P (sc x)
+    double carry = sc * readlane_d(rx[0], 0);
+    for (int b = 0; b < nblk; ++b) {
+      const int bits = __builtin_amdgcn_readlane(rpv, b);
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        const int i = SPL * b + s;
+        if (i < nf) {
+          const double xn = s + 1 < SPL ? readlane_d(rx[(s + 1) % SPL], b)
+                                        : readlane_d(rx[0], b + 1);
+          const double y = sc * xn;
+          const double m = readlane_d(rm[s], b);
+          double out;
+          if ((bits >> s) & 1) { out = y; carry = carry - m * y; }
+          else { out = carry; carry = y - m * carry; }
+          rx[s] = put(rx[s], out, b);
+        }
+      }
+    }
+    // row nf takes carry; backward: U^-1 with the largest magnitude
+    {
+      const int b = nf / SPL;
+#pragma unroll
+      for (int s = 0; s < SPL; ++s)
+        if (s == nf % SPL) rx[s] = put(rx[s], carry, b);
+    }
+    double x1 = 0.0, x2 = 0.0, mx = 0.0;
+    for (int b = nf / SPL; b >= 0; --b) {
+#pragma unroll
+      for (int s = SPL - 1; s >= 0; --s) {
+        const int i = SPL * b + s;
+        if (i <= nf) {
+          const double xi = (readlane_d(rx[s], b) - readlane_d(ru1[s], b) * x1 -
+                             readlane_d(ru2[s], b) * x2) * readlane_d(ru0[s], b);
+          rx[s] = put(rx[s], xi, b);
+          mx = fmax(mx, fabs(xi));
+          x2 = x1; x1 = xi;
+        }
+      }
+    }
+    sc = 1.0 / mx;
+  }
+  // normalisation: the rows through LDS, a wave sum of their squares
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int i = SPL * lane + s;
+    if (i < n) xs[i] = rx[s];
   }
   __syncthreads();
-  if (lane == 0) {
-    const double tol = kEps * bn;
-    double cd = sd[0] - lam, cs = se[0];
-#pragma unroll 2
-    for (int i = 0; i < n - 1; ++i) {
-      const double ci = se[i];
-      const double an = sd[i + 1] - lam;
-      const double bnx = i + 1 < n - 1 ? se[i + 1] : 0.0;
-      const bool pv = fabs(ci) > fabs(cd);
-      double u0, u1, u2, m;
-      if (pv) {
-        u0 = ci; u1 = an; u2 = bnx;
-        m = cd / ci;
-        const double ncd = cs - m * an;
-        cs = -m * bnx;
-        cd = ncd;
-      } else {
-        if (cd == 0.0) cd = tol;
-        u0 = cd; u1 = cs; u2 = 0.0;
-        m = ci / cd;
-        cd = an - m * cs;
-        cs = bnx;
-      }
-      if (fabs(u0) < tol) u0 = u0 >= 0.0 ? tol : -tol;
-      U0[i] = 1.0 / u0; U1[i] = u1; U2[i] = u2; Mm[i] = m; Pv[i] = pv;
-    }
-    if (fabs(cd) < tol) cd = cd >= 0.0 ? tol : -tol;
-    U0[n - 1] = 1.0 / cd;
-    const int nf = n - 1;
-    double sc = 1.0;
-    for (int it = 0; it < kInvIters; ++it) {
-      double carry = sc * x[0];
-#pragma unroll 4
-      for (int i = 0; i < nf; ++i) {
-        const double y = sc * x[i + 1];
-        const double m = Mm[i];
-        if (Pv[i]) { x[i] = y; carry = carry - m * y; }
-        else { x[i] = carry; carry = y - m * carry; }
-      }
-      double x2 = carry * U0[nf];
-      x[nf] = x2;
-      double x1 = (x[nf - 1] - U1[nf - 1] * x2) * U0[nf - 1];
-      x[nf - 1] = x1;
-      double mx = fmax(fabs(x1), fabs(x2));
-#pragma unroll 4
-      for (int i = nf - 2; i >= 0; --i) {
-        const double xi = (x[i] - U1[i] * x1 - U2[i] * x2) * U0[i];
-        x[i] = xi;
-        mx = fmax(mx, fabs(xi));
-        x2 = x1; x1 = xi;
-      }
-      sc = 1.0 / mx;
-    }
-    sc_s = sc;
-  }
-  __syncthreads();
-  const double sc = sc_s;
   double s2 = 0.0;
   for (int i = lane; i < n; i += 64) {
-    const double v = sc * x[i];
+    const double v = sc * xs[i];
     s2 += v * v;
   }
   s2 = wave_sum(s2);
   const double f = sc / sqrt(s2);
-  for (int i = lane; i < n; i += 64) Z[(size_t)(b0 + i) * N + t] = x[i] * f;
+  for (int i = lane; i < n; i += 64) Z[(size_t)(b0 + i) * N + t] = xs[i] * f;
 }
 
 // grid (ceil(N / 4), nH), 256 threads: the wave of eigenvalue t acts if t
@@ -1362,12 +1408,12 @@ hipError_t spectral_batch(const ProbDesc* probs, int nH, const MatDesc* descs,
   mark_begin(K_SPECTRUM, st);
   hipLaunchKernelGGL(bisect_kernel, dim3((N + 3) / 4, nH), dim3(256),
                      sizeof(double) * 2 * N, st, N, E);
-  if (N <= kInvLdsMax) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(invit_lds_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)invit_lds_bytes(N));
-    hipLaunchKernelGGL(invit_lds_kernel, dim3(N, nH), dim3(64),
-                       invit_lds_bytes(N), st, N, E);
+  if (N <= 512) {
+    hipLaunchKernelGGL(invit_reg_kernel<8>, dim3(N, nH), dim3(64),
+                       sizeof(double) * 3 * N, st, N, E);
+  } else if (N <= 1024) {
+    hipLaunchKernelGGL(invit_reg_kernel<16>, dim3(N, nH), dim3(64),
+                       sizeof(double) * 3 * N, st, N, E);
   } else {
     hipLaunchKernelGGL(invit_kernel, dim3((N + 63) / 64, nH), dim3(64),
                        sizeof(double) * 2 * N, st, N, E);
