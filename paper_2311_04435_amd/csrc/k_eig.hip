@@ -825,6 +825,7 @@ invit_reg_kernel(int N, EigBufs E) {
     rx[s] = i < n ? hash_uniform(seed | (unsigned)i) : 0.0;
     ru0[s] = 0.0; ru1[s] = 0.0; ru2[s] = 0.0; rm[s] = 0.0;
   }
+  static_assert(SPL <= 32, "the pivot bits of a lane's rows fill one int");
   int rpv = 0;   // bit s: row SPL lane + s pivoted
   // lane dst takes v (the same value in every lane), the others keep old
   auto put = [&](double old, double v, int dst) { return lane == dst ? v : old; };
